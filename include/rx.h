@@ -1,0 +1,209 @@
+/*
+ * rx.h -- C interface of the MI355X lockstep regular expression matcher.
+ *
+ * The library implements the lockstep construction of Rathnayake & Thielecke,
+ * "Regular Expression Matching and Operational Semantics" (SOS 2011): an
+ * expression is laid out as a heap of nodes with continuation pointers
+ * (Section 4, Def. 4.1 and Def. 4.4), and every input byte advances the whole
+ * set of live threads at once (Section 5, Def. 5.2 / 5.3), duplicate threads
+ * collapsing by pointer equality (the remark closing Section 3).  Thread sets
+ * are bitsets over node indices; the per-byte macro step runs in hand-written
+ * HIP kernels for gfx950.
+ *
+ * Conventions for every call:
+ *   - Every function returns an int status: RX_OK (0) or a negative RX_E*
+ *     code.  Nothing throws across this interface.  On failure a message is
+ *     available from rx_last_error() on the same host thread.
+ *   - Pointers named d_* are device pointers on the current HIP device (for
+ *     example the data_ptr() of a torch tensor); everything else is host
+ *     memory.  The caller owns every buffer it passes in.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is enqueued on it asynchronously; the library never
+ *     synchronises the stream unless a call says so.
+ */
+#ifndef RX_H
+#define RX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+    RX_OK = 0,
+    RX_EINVAL = -1,        /* malformed AST or bad argument */
+    RX_ETOOBIG = -2,       /* program above a kernel limit, or request above a budget */
+    RX_ENOTUPLOADED = -3,  /* rx_match on a program without device tables */
+    RX_EHIP = -4,          /* a HIP runtime call failed; message holds its error string */
+    RX_EBUSY = -5,         /* server over its memory budget in non-blocking mode */
+    RX_ENOMEM = -6,        /* host allocation failed */
+    RX_EJIT = -7,          /* run-time kernel generation or compilation failed */
+    RX_ETIMEOUT = -8       /* a wait reached its deadline */
+};
+
+/* Node kinds.  EPS, BYTE, CAT (concatenation), ALT and STAR are the grammar of
+ * Section 2.  CLASS (a set of bytes), PLUS (one or more) and OPT (zero or one)
+ * extend it: a CLASS leaf x moves x --a--> cont x for every byte a in its set;
+ * OPT p moves to its child and to cont p, and its child's continuation is
+ * cont p; PLUS p moves to its child, whose continuation is a companion loop
+ * node q (RX_PLUSLOOP, created by rx_compile) that moves to the child and to
+ * cont p. */
+enum {
+    RX_EPS = 0,
+    RX_BYTE = 1,
+    RX_CLASS = 2,
+    RX_CAT = 3,
+    RX_ALT = 4,
+    RX_STAR = 5,
+    RX_PLUS = 6,
+    RX_OPT = 7,
+    RX_PLUSLOOP = 8 /* only in compiled programs, never in an input AST */
+};
+
+/* rx_compile flags. */
+enum {
+    RX_SEARCH = 1u /* match .*(e).* (any substring) instead of the whole string */
+};
+
+/* One AST node.  Children are indices into the same array; an unused child is
+ * -1.  BYTE uses `byte`, CLASS uses `cls` (an index into the class array). */
+typedef struct {
+    uint8_t kind;
+    uint8_t byte;
+    uint16_t cls;
+    int32_t c0, c1;
+} rx_ast_node;
+
+/* A set of bytes: byte b is bit (b & 63) of bits[b >> 6]. */
+typedef struct {
+    uint64_t bits[4];
+} rx_class;
+
+/* One node of a compiled program's node array d[] (the heap of Def. 4.1).
+ * label: the byte of a BYTE leaf, the class index of a CLASS leaf (the search
+ * wrapper's any-byte class is appended after the caller's classes), -1
+ * otherwise.  cont: the continuation pointer of Def. 4.4, -1 for null. */
+typedef struct {
+    int32_t kind, c0, c1, label, cont;
+} rx_node;
+
+/* Facts about a compiled program. */
+typedef struct {
+    int32_t m;           /* nodes in d[], including search wrapper and PLUS companions */
+    int32_t n_leaves;    /* L: leaves (BYTE and CLASS nodes); the accept bit has index L */
+    int32_t words;       /* 32-bit words per thread set: ceil((L + 1) / 32) */
+    int32_t nullable;    /* 1 if the empty string is accepted */
+    int32_t suffix_any;  /* 1 if the root is (e)(any byte)*: acceptance is then absorbing */
+    int32_t search;      /* 1 if compiled with RX_SEARCH */
+    int64_t table_bytes; /* device bytes rx_program_upload needs */
+    int32_t depth;       /* height of the node tree (root = 0) */
+    int32_t n_classes;   /* classes including the wrapper's any-byte class */
+} rx_info;
+
+typedef struct rx_program rx_program; /* opaque; owned by the library */
+
+/*
+ * rx_compile -- validate an AST and build its program.
+ *
+ * Checks (Def. 4.3 with the disjoint union of Def. 4.2): kinds in range,
+ * children in range, every node except `root` has exactly one parent, the
+ * root none, every node reachable from the root (so there are no cycles),
+ * class indices < n_classes.  The tree is packed into d[] in breadth-first
+ * order with the root at d[0] (Section 8: the root node is the one scheduled
+ * first); PLUS companions follow the tree nodes.  cont is wired by a second,
+ * iterative pass (Def. 4.4).  Then the evolution tables of Def. 5.1 are
+ * precomputed: First = the leaves (and accept bit) reachable from the root by
+ * non-consuming moves, Follow[x] = those reachable from cont x, and for each
+ * byte b the set of leaves whose label holds b.
+ *
+ * ast/n_ast/root: the tree; classes/n_classes: its byte classes (may be NULL
+ * when n_classes is 0); flags: RX_SEARCH or 0.  On success *out owns a new
+ * program (free it with rx_program_free).  Errors: RX_EINVAL (malformed),
+ * RX_ETOOBIG (more than 4095 leaves or 2^20 nodes), RX_ENOMEM.
+ */
+int rx_compile(const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx_class* classes,
+               int32_t n_classes, uint32_t flags, rx_program** out);
+
+/* Frees the program and its host tables.  Device memory handed to
+ * rx_program_upload stays the caller's.  NULL is ignored. */
+void rx_program_free(rx_program* prog);
+
+/* Fills *out.  Errors: RX_EINVAL on NULL arguments. */
+int rx_program_info(const rx_program* prog, rx_info* out);
+
+/* Copies the node array d[] (with cont) into out[0 .. min(cap, m)) and sets
+ * *m to the program's node count.  out may be NULL to query m only. */
+int rx_program_nodes(const rx_program* prog, rx_node* out, int32_t cap, int32_t* m);
+
+/*
+ * Copies the evolution tables (Def. 5.1) to host memory, each optional (NULL
+ * skips it).  Sets are `words` 32-bit words, leaf rank r is bit (r & 31) of
+ * word r >> 5 and the accept bit is rank L.
+ *   first[words]            -- the evolution of {root}
+ *   follow[L * words]       -- row r: the evolution of {cont x} for the leaf x of rank r
+ *   bytemask[256 * words]   -- row b: the leaves whose label holds byte b
+ *   leaf_node[L]            -- the d[] index of the leaf of each rank
+ */
+int rx_program_sets(const rx_program* prog, uint32_t* first, uint32_t* follow, uint32_t* bytemask,
+                    int32_t* leaf_node);
+
+/*
+ * Copies the program's device tables into d_buf (at least info.table_bytes
+ * bytes, 256-byte aligned, on the current device) with an asynchronous copy
+ * on `stream`, and records d_buf in the program.  The caller keeps d_buf
+ * alive while the program is matched.  Errors: RX_EINVAL, RX_ETOOBIG (cap too
+ * small), RX_EHIP.
+ */
+int rx_program_upload(rx_program* prog, void* d_buf, size_t cap, void* stream);
+
+/*
+ * rx_match -- one match bit per string (the lockstep machine of Def. 5.3).
+ *
+ * String i is d_bytes[d_offsets[i] .. d_offsets[i+1]); offsets are int64 and
+ * must satisfy 0 <= offsets[i] <= offsets[i+1] (not checked on the device).
+ * d_out[i] is set to 1 if string i is in the language (a substring of it, for
+ * RX_SEARCH), else 0.  Runs asynchronously on `stream`; allocates nothing.
+ * n == 0 is a no-op.  The kernel variant is chosen from the program's size:
+ * one lane per string for sets of up to 16 words, one wavefront per string
+ * above that.  Errors: RX_EINVAL, RX_ENOTUPLOADED, RX_EHIP.
+ */
+int rx_match(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t n,
+             uint8_t* d_out, void* stream);
+
+/* Kernel variants for rx_match_ex. */
+enum {
+    RX_VARIANT_AUTO = 0,
+    RX_VARIANT_LANE = 1,   /* one lane owns one string and its set (sets of <= 16 words) */
+    RX_VARIANT_WAVE = 2,   /* one wavefront owns one string; lane j owns word j of the set */
+    RX_VARIANT_SLICED = 3  /* bit-sliced node circuit: one lane runs 32 strings at once
+                              (needs rx_program_jit) */
+};
+
+/* Launch parameters; zero fields mean "default". */
+typedef struct {
+    int32_t variant;        /* RX_VARIANT_* */
+    int32_t block;          /* threads per workgroup (multiple of 64, <= 1024) */
+    int32_t grid;           /* workgroups (0 = enough for one pass over the strings) */
+    int32_t unroll;         /* variant-specific inner unroll (sliced: bytes per load) */
+} rx_launch;
+
+/* rx_match with an explicit kernel variant and launch shape (the autotuner's
+ * entry point).  Every variant returns the same bits (Thm. 7.2: the parallel
+ * schedule does not change the result). */
+int rx_match_ex(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t n,
+                uint8_t* d_out, const rx_launch* launch, void* stream);
+
+/* Thread-local message of the last failed call on this host thread. */
+const char* rx_last_error(void);
+
+/* Library version string. */
+const char* rx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RX_H */

@@ -1,0 +1,200 @@
+// C interface of the lockstep matcher: program lifetime, upload and launch
+// selection.  Every entry point catches everything and reports through a
+// thread-local message.
+#include <cstring>
+#include <exception>
+#include <string>
+
+#include "rx_internal.h"
+
+namespace rx {
+
+namespace {
+thread_local std::string g_error;
+}
+
+const char* last_error_cstr() { return g_error.c_str(); }
+
+int fail(int code, const std::string& msg) {
+    g_error = msg;
+    return code;
+}
+
+void clear_error() { g_error.clear(); }
+
+static int hip_fail(int err, const char* what) {
+    return fail(RX_EHIP, std::string(what) + ": " + hip_error_string(err));
+}
+
+int make_launch_args(const Program* P, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t n,
+                     uint8_t* d_out, void* stream, LaunchArgs* a) {
+    if (!P) return fail(RX_EINVAL, "program is NULL");
+    if (n < 0) return fail(RX_EINVAL, "negative string count");
+    if (n > 0 && (!d_bytes || !d_offsets || !d_out)) return fail(RX_EINVAL, "NULL device buffer");
+    if (!P->dev) return fail(RX_ENOTUPLOADED, "program has not been uploaded (rx_program_upload)");
+    const uint8_t* base = static_cast<const uint8_t*>(P->dev);
+    a->first = reinterpret_cast<const uint32_t*>(base + P->layout.first);
+    a->follow = reinterpret_cast<const uint32_t*>(base + P->layout.follow);
+    a->bytemask = reinterpret_cast<const uint32_t*>(base + P->layout.bytemask);
+    a->L = P->L;
+    a->W = P->W;
+    a->suffix_any = P->suffix_any ? 1 : 0;
+    a->bytes = d_bytes;
+    a->offsets = d_offsets;
+    a->n = n;
+    a->out = d_out;
+    a->block = 0;
+    a->grid = 0;
+    a->unroll = 0;
+    a->stream = stream;
+    return RX_OK;
+}
+
+}  // namespace rx
+
+using namespace rx;
+
+#define RX_GUARD_BEGIN try {
+#define RX_GUARD_END                                                          \
+    }                                                                         \
+    catch (const std::bad_alloc&) {                                           \
+        return fail(RX_ENOMEM, "out of host memory");                         \
+    }                                                                         \
+    catch (const std::exception& e) {                                         \
+        return fail(RX_EINVAL, std::string("internal error: ") + e.what());   \
+    }                                                                         \
+    catch (...) {                                                             \
+        return fail(RX_EINVAL, "internal error");                             \
+    }
+
+extern "C" {
+
+int rx_compile(const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx_class* classes,
+               int32_t n_classes, uint32_t flags, rx_program** out) {
+    RX_GUARD_BEGIN
+    if (!out) return fail(RX_EINVAL, "out is NULL");
+    *out = nullptr;
+    Program* P = nullptr;
+    int rc = compile(ast, n_ast, root, classes, n_classes, flags, &P);
+    if (rc) return rc;
+    // the C handle is an opaque pointer to the library's Program
+    *out = reinterpret_cast<rx_program*>(P);
+    clear_error();
+    return RX_OK;
+    RX_GUARD_END
+}
+
+void rx_program_free(rx_program* prog) {
+    try {
+        delete reinterpret_cast<Program*>(prog);
+    } catch (...) {
+    }
+}
+
+int rx_program_info(const rx_program* prog, rx_info* out) {
+    if (!prog || !out) return fail(RX_EINVAL, "NULL argument");
+    const Program* P = reinterpret_cast<const Program*>(prog);
+    std::memset(out, 0, sizeof(*out));
+    out->m = P->m;
+    out->n_leaves = P->L;
+    out->words = P->W;
+    out->nullable = P->nullable;
+    out->suffix_any = P->suffix_any;
+    out->search = (P->flags & RX_SEARCH) ? 1 : 0;
+    out->table_bytes = P->layout.total;
+    out->depth = P->height;
+    out->n_classes = (int32_t)P->classes.size();
+    return RX_OK;
+}
+
+int rx_program_nodes(const rx_program* prog, rx_node* out, int32_t cap, int32_t* m) {
+    if (!prog) return fail(RX_EINVAL, "program is NULL");
+    const Program* P = reinterpret_cast<const Program*>(prog);
+    if (m) *m = P->m;
+    if (out) {
+        const int32_t k = cap < P->m ? cap : P->m;
+        for (int32_t i = 0; i < k; ++i) {
+            out[i].kind = P->kind[i];
+            out[i].c0 = P->c0[i];
+            out[i].c1 = P->c1[i];
+            out[i].label = P->label[i];
+            out[i].cont = P->cont[i];
+        }
+    }
+    return RX_OK;
+}
+
+int rx_program_sets(const rx_program* prog, uint32_t* first, uint32_t* follow, uint32_t* bytemask,
+                    int32_t* leaf_node) {
+    if (!prog) return fail(RX_EINVAL, "program is NULL");
+    const Program* P = reinterpret_cast<const Program*>(prog);
+    if (first) std::memcpy(first, P->first.data(), 4 * P->first.size());
+    if (follow && !P->follow.empty()) std::memcpy(follow, P->follow.data(), 4 * P->follow.size());
+    if (bytemask) std::memcpy(bytemask, P->bytemask.data(), 4 * P->bytemask.size());
+    if (leaf_node && !P->leaf_node.empty()) std::memcpy(leaf_node, P->leaf_node.data(), 4 * P->leaf_node.size());
+    return RX_OK;
+}
+
+int rx_program_upload(rx_program* prog, void* d_buf, size_t cap, void* stream) {
+    RX_GUARD_BEGIN
+    if (!prog || !d_buf) return fail(RX_EINVAL, "NULL argument");
+    Program* P = reinterpret_cast<Program*>(prog);
+    if ((reinterpret_cast<uintptr_t>(d_buf) & 255) != 0) return fail(RX_EINVAL, "device buffer must be 256-byte aligned");
+    if (cap < (size_t)P->layout.total)
+        return fail(RX_ETOOBIG, "device buffer holds " + std::to_string(cap) + " bytes; the program needs " +
+                                    std::to_string(P->layout.total));
+    int dev = -1;
+    if (int e = hip_current_device(&dev)) return hip_fail(e, "hipGetDevice");
+    if (int e = hip_memcpy_h2d_async(d_buf, P->blob.data(), P->blob.size(), stream)) return hip_fail(e, "hipMemcpyAsync");
+    P->dev = d_buf;
+    P->dev_id = dev;
+    clear_error();
+    return RX_OK;
+    RX_GUARD_END
+}
+
+int rx_match_ex(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t n,
+                uint8_t* d_out, const rx_launch* launch, void* stream) {
+    RX_GUARD_BEGIN
+    LaunchArgs a;
+    if (int rc = make_launch_args(reinterpret_cast<const Program*>(prog), d_bytes, d_offsets, n, d_out, stream, &a)) return rc;
+    if (n == 0) return RX_OK;
+    const Program* P = reinterpret_cast<const Program*>(prog);
+    int variant = launch ? launch->variant : RX_VARIANT_AUTO;
+    if (launch) {
+        if (launch->block < 0 || launch->block > 1024 || (launch->block % 64) != 0)
+            return fail(RX_EINVAL, "block must be a multiple of 64 in [64, 1024]");
+        if (launch->grid < 0) return fail(RX_EINVAL, "negative grid");
+        a.block = launch->block;
+        a.grid = launch->grid;
+        a.unroll = launch->unroll;
+    }
+    if (variant == RX_VARIANT_AUTO) variant = P->W <= kLaneMaxWords ? RX_VARIANT_LANE : RX_VARIANT_WAVE;
+    int e;
+    switch (variant) {
+    case RX_VARIANT_LANE:
+        if (P->W > kLaneMaxWords) return fail(RX_ETOOBIG, "the lane kernel holds sets of at most 16 words");
+        if (a.block > 256) return fail(RX_EINVAL, "the lane kernel runs at most 256 threads per workgroup");
+        e = launch_lane(a);
+        break;
+    case RX_VARIANT_WAVE:
+        if (P->W > kWaveMaxWords) return fail(RX_ETOOBIG, "the wavefront kernel holds sets of at most 128 words");
+        e = launch_wave(a);
+        break;
+    default: return fail(RX_EINVAL, "unknown or unavailable kernel variant");
+    }
+    if (e) return hip_fail(e, "kernel launch");
+    return RX_OK;
+    RX_GUARD_END
+}
+
+int rx_match(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t n,
+             uint8_t* d_out, void* stream) {
+    return rx_match_ex(prog, d_bytes, d_offsets, n, d_out, nullptr, stream);
+}
+
+const char* rx_last_error(void) { return last_error_cstr(); }
+
+const char* rx_version(void) { return "rx-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

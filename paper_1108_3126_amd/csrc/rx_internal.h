@@ -1,0 +1,79 @@
+// Internal declarations shared by the host compiler, the C interface and the
+// kernel launchers of the lockstep matcher.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "rx.h"
+
+namespace rx {
+
+constexpr int kMaxLeaves = 4095;        // accept bit is rank L, so sets hold <= 4096 bits
+constexpr int kMaxNodes = 1 << 20;
+constexpr int kLaneMaxWords = 16;       // one-lane-per-string kernel limit (L <= 511)
+constexpr int kWaveMaxWords = 128;      // wavefront kernel limit: lane j owns words j and j+64
+
+// Device table layout (all offsets in bytes from the start of the uploaded
+// buffer, each section 256-byte aligned).
+struct DevLayout {
+    int64_t first = 0;      // words u32
+    int64_t follow = 0;     // L * words u32
+    int64_t bytemask = 0;   // 256 * words u32
+    int64_t total = 0;
+};
+
+struct Program {
+    // node array d[] (the heap), breadth-first from the root at index 0
+    std::vector<int32_t> kind, c0, c1, label, cont, depth;
+    std::vector<std::array<uint64_t, 4>> classes;  // caller's classes + wrapper's any-byte class
+    int32_t m = 0, n_tree = 0;
+    uint32_t flags = 0;
+    int32_t L = 0, W = 0, height = 0;
+    bool nullable = false, suffix_any = false;
+    std::vector<int32_t> leaf_node;  // rank -> node
+    std::vector<int32_t> leaf_rank;  // node -> rank, -1 for internal nodes
+    // evolution tables (Def. 5.1), 32-bit words
+    std::vector<uint32_t> first, follow, bytemask;
+    DevLayout layout;
+    std::vector<uint8_t> blob;       // host image of the device tables
+    // device state
+    void* dev = nullptr;
+    int dev_id = -1;
+    // run-time generated kernel for the bit-sliced circuit (may be null)
+    void* jit = nullptr;
+};
+
+// error reporting (thread-local message)
+int fail(int code, const std::string& msg);
+void clear_error();
+const char* last_error_cstr();
+
+// host compiler (rx_compile.cpp)
+int compile(const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx_class* classes,
+            int32_t n_classes, uint32_t flags, Program** out);
+
+// device launchers (rx_kernels.hip); return a hipError_t as int
+struct LaunchArgs {
+    const uint32_t* first;
+    const uint32_t* follow;
+    const uint32_t* bytemask;
+    int32_t L, W;
+    int32_t suffix_any;
+    const uint8_t* bytes;
+    const int64_t* offsets;
+    int64_t n;
+    uint8_t* out;
+    int32_t block, grid, unroll;
+    void* stream;
+};
+int launch_lane(const LaunchArgs& a);
+int launch_wave(const LaunchArgs& a);
+const char* hip_error_string(int err);
+int hip_current_device(int* dev);
+int hip_memcpy_h2d_async(void* dst, const void* src, size_t n, void* stream);
+int hip_cu_count(int* cus);
+
+}  // namespace rx

@@ -1,0 +1,259 @@
+// Table-form lockstep kernels for gfx950.
+//
+// One macro step of the generic lockstep machine (Def. 5.2 / 5.3, Rathnayake &
+// Thielecke, SOS 2011) on a bitset thread set S over leaf ranks:
+//     X  = S & Mask[c]              -- the synchronised move on byte c: only
+//                                      leaves whose label holds c survive
+//     S' = OR_{x in X} Follow[x]    -- each survivor moves to its continuation
+//                                      and is evolved (Def. 5.1); OR-ing the
+//                                      precomputed evolutions is exactly the
+//                                      removal of duplicate threads by pointer
+//                                      equality.
+// The accept bit (null) has rank L and is never in Mask[c], so a thread that
+// reached null dies when input remains.  A string is accepted when the accept
+// bit is in S after its last byte.
+//
+// Two layouts:
+//   k_lane<W>  one lane owns one string and its W-word set in registers;
+//              Mask and Follow are staged once per workgroup in LDS.
+//   k_wave<>   one wavefront owns one string; lane j owns words j and j+64 of
+//              the set; survivors are enumerated wave-uniformly with ballot.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "rx_internal.h"
+
+namespace rx {
+
+namespace {
+
+struct KArgs {
+    const uint32_t* first;
+    const uint32_t* follow;
+    const uint32_t* bytemask;
+    int32_t L, W, suffix_any, pad;
+    const uint8_t* bytes;
+    const int64_t* offsets;
+    int64_t n;
+    uint8_t* out;
+};
+
+template <int W>
+__device__ __forceinline__ uint32_t pick(const uint32_t (&S)[W], int w) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) r |= (i == w) ? S[i] : 0u;
+    return r;
+}
+
+template <int W>
+__device__ __forceinline__ void lane_step(uint32_t (&S)[W], uint32_t c, const uint32_t* __restrict__ M,
+                                          const uint32_t* __restrict__ F) {
+    uint32_t X[W];
+    const uint32_t* mrow = M + c * W;
+#pragma unroll
+    for (int w = 0; w < W; ++w) X[w] = S[w] & mrow[w];
+#pragma unroll
+    for (int w = 0; w < W; ++w) S[w] = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        uint32_t x = X[w];
+        while (x) {
+            const int b = __builtin_ctz(x);
+            x &= x - 1;
+            const uint32_t* row = F + (w * 32 + b) * W;
+#pragma unroll
+            for (int v = 0; v < W; ++v) S[v] |= row[v];
+        }
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_lane(KArgs a) {
+    extern __shared__ uint32_t lds[];
+    uint32_t* M = lds;
+    uint32_t* F = lds + 256 * W;
+    for (int i = threadIdx.x; i < 256 * W; i += blockDim.x) M[i] = a.bytemask[i];
+    for (int i = threadIdx.x; i < a.L * W; i += blockDim.x) F[i] = a.follow[i];
+    __syncthreads();
+    const int aw = a.L >> 5;
+    const uint32_t abit = 1u << (a.L & 31);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t sid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; sid < a.n; sid += stride) {
+        uint32_t S[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) S[w] = a.first[w];
+        const int64_t lo = a.offsets[sid], hi = a.offsets[sid + 1];
+        int res = -1;
+        // aligned 16-byte blocks of the absolute address range [bytes+lo, bytes+hi):
+        // every block read holds at least one byte of the string
+        const int64_t skew = (int64_t)(reinterpret_cast<uintptr_t>(a.bytes) & 15);
+        for (int64_t base = ((lo + skew) & ~int64_t(15)) - skew; base < hi; base += 16) {
+            const uint4 v = *reinterpret_cast<const uint4*>(a.bytes + base);
+            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+            const int b0 = lo > base ? (int)(lo - base) : 0;
+            const int b1 = hi - base < 16 ? (int)(hi - base) : 16;
+#pragma unroll
+            for (int b = 0; b < 16; ++b) {
+                if (b >= b0 && b < b1) lane_step<W>(S, (wv[b >> 2] >> (8 * (b & 3))) & 255u, M, F);
+            }
+            uint32_t any = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) any |= S[w];
+            if (any == 0) { res = 0; break; }                          // no live thread: reject
+            if (a.suffix_any && (pick<W>(S, aw) & abit)) { res = 1; break; }  // accept is absorbing
+        }
+        if (res < 0) res = (pick<W>(S, aw) & abit) ? 1 : 0;
+        a.out[sid] = (uint8_t)res;
+    }
+}
+
+// One wavefront per string.  Lane j owns words j and j + 64 of the set.
+template <bool TABLES_IN_LDS>
+__global__ __launch_bounds__(1024) void k_wave(KArgs a) {
+    extern __shared__ uint32_t lds[];
+    const int W = a.W, L = a.L;
+    const uint32_t* M = a.bytemask;
+    const uint32_t* F = a.follow;
+    if (TABLES_IN_LDS) {
+        uint32_t* Ml = lds;
+        uint32_t* Fl = lds + 256 * W;
+        for (int i = threadIdx.x; i < 256 * W; i += blockDim.x) Ml[i] = a.bytemask[i];
+        for (int i = threadIdx.x; i < L * W; i += blockDim.x) Fl[i] = a.follow[i];
+        __syncthreads();
+        M = Ml;
+        F = Fl;
+    }
+    const int lane = threadIdx.x & 63;
+    const int waves = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool own0 = lane < W, own1 = lane + 64 < W;
+    const int aw = L >> 5;
+    const uint32_t abit = 1u << (L & 31);
+    for (int64_t sid = (int64_t)blockIdx.x * waves + wave; sid < a.n; sid += (int64_t)gridDim.x * waves) {
+        uint32_t S0 = own0 ? a.first[lane] : 0u;
+        uint32_t S1 = own1 ? a.first[lane + 64] : 0u;
+        const int64_t lo = a.offsets[sid], hi = a.offsets[sid + 1];
+        int res = -1;
+        const int64_t skew = (int64_t)(reinterpret_cast<uintptr_t>(a.bytes) & 3);
+        for (int64_t base = ((lo + skew) & ~int64_t(3)) - skew; base < hi && res < 0; base += 4) {
+            const uint32_t word = *reinterpret_cast<const uint32_t*>(a.bytes + base);
+            const int b0 = lo > base ? (int)(lo - base) : 0;
+            const int b1 = hi - base < 4 ? (int)(hi - base) : 4;
+            for (int b = b0; b < b1; ++b) {
+                const uint32_t c = (word >> (8 * b)) & 255u;
+                const uint32_t X0 = own0 ? (S0 & M[c * W + lane]) : 0u;
+                const uint32_t X1 = own1 ? (S1 & M[c * W + 64 + lane]) : 0u;
+                uint32_t N0 = 0, N1 = 0;
+                for (int half = 0; half < 2; ++half) {
+                    uint64_t nz = __ballot((half ? X1 : X0) != 0);
+                    while (nz) {
+                        const int wl = __builtin_ctzll(nz);
+                        nz &= nz - 1;
+                        uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)(half ? X1 : X0), wl);
+                        const int wordidx = wl + 64 * half;
+                        while (xw) {
+                            const int bit = __builtin_ctz(xw);
+                            xw &= xw - 1;
+                            const uint32_t* row = F + (size_t)(wordidx * 32 + bit) * W;
+                            if (own0) N0 |= row[lane];
+                            if (own1) N1 |= row[lane + 64];
+                        }
+                    }
+                }
+                S0 = N0;
+                S1 = N1;
+            }
+            const bool live = __ballot((S0 | S1) != 0) != 0;
+            if (!live) { res = 0; break; }
+            if (a.suffix_any) {
+                const uint32_t sw = (uint32_t)__builtin_amdgcn_readlane((int)(aw < 64 ? S0 : S1), aw & 63);
+                if (sw & abit) { res = 1; break; }
+            }
+        }
+        if (res < 0) {
+            const uint32_t sw = (uint32_t)__builtin_amdgcn_readlane((int)(aw < 64 ? S0 : S1), aw & 63);
+            res = (sw & abit) ? 1 : 0;
+        }
+        if (lane == 0) a.out[sid] = (uint8_t)res;
+    }
+}
+
+KArgs kargs(const LaunchArgs& a) {
+    KArgs k;
+    k.first = a.first;
+    k.follow = a.follow;
+    k.bytemask = a.bytemask;
+    k.L = a.L;
+    k.W = a.W;
+    k.suffix_any = a.suffix_any;
+    k.pad = 0;
+    k.bytes = a.bytes;
+    k.offsets = a.offsets;
+    k.n = a.n;
+    k.out = a.out;
+    return k;
+}
+
+template <int W>
+int launch_lane_w(const LaunchArgs& a) {
+    const int block = a.block > 0 ? a.block : 256;
+    int64_t need = (a.n + block - 1) / block;
+    int grid = a.grid > 0 ? a.grid : (int)(need < (1 << 30) ? need : (1 << 30));
+    if (grid < 1) grid = 1;
+    const size_t lds = 4 * (size_t)(256 + a.L) * W;
+    hipLaunchKernelGGL(k_lane<W>, dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
+    return (int)hipGetLastError();
+}
+
+}  // namespace
+
+int launch_lane(const LaunchArgs& a) {
+    switch (a.W) {
+#define RX_LANE_CASE(w) \
+    case w: return launch_lane_w<w>(a);
+        RX_LANE_CASE(1) RX_LANE_CASE(2) RX_LANE_CASE(3) RX_LANE_CASE(4) RX_LANE_CASE(5) RX_LANE_CASE(6)
+        RX_LANE_CASE(7) RX_LANE_CASE(8) RX_LANE_CASE(9) RX_LANE_CASE(10) RX_LANE_CASE(11) RX_LANE_CASE(12)
+        RX_LANE_CASE(13) RX_LANE_CASE(14) RX_LANE_CASE(15) RX_LANE_CASE(16)
+#undef RX_LANE_CASE
+    default: return (int)hipErrorInvalidValue;
+    }
+}
+
+int launch_wave(const LaunchArgs& a) {
+    const int block = a.block > 0 ? a.block : 256;
+    const int waves = block / 64;
+    int64_t need = (a.n + waves - 1) / waves;
+    int grid = a.grid > 0 ? a.grid : (int)(need < (1 << 30) ? need : (1 << 30));
+    if (grid < 1) grid = 1;
+    const size_t lds = 4 * (size_t)(256 + a.L) * a.W;
+    if (lds <= 150 * 1024) {
+        static bool attr_set = false;
+        if (!attr_set) {
+            hipFuncSetAttribute((const void*)k_wave<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr_set = true;
+        }
+        hipLaunchKernelGGL(k_wave<true>, dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
+    } else {
+        hipLaunchKernelGGL(k_wave<false>, dim3(grid), dim3(block), 0, (hipStream_t)a.stream, kargs(a));
+    }
+    return (int)hipGetLastError();
+}
+
+const char* hip_error_string(int err) { return hipGetErrorString((hipError_t)err); }
+
+int hip_current_device(int* dev) { return (int)hipGetDevice(dev); }
+
+int hip_memcpy_h2d_async(void* dst, const void* src, size_t n, void* stream) {
+    return (int)hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, (hipStream_t)stream);
+}
+
+int hip_cu_count(int* cus) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    return (int)hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
+}
+
+}  // namespace rx

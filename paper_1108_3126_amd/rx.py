@@ -1,0 +1,214 @@
+"""Python binding of the C interface in include/rx.h (ctypes; argument
+marshalling only -- every step of matching runs in the HIP library).
+
+PyTorch supplies device memory and streams: strings, offsets and results are
+torch tensors on the GPU, and calls are enqueued on the current torch stream.
+The library must have been built (``python -m paper_1108_3126_amd.build``);
+importing this module fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librx.so")
+
+RX_OK, RX_EINVAL, RX_ETOOBIG, RX_ENOTUPLOADED, RX_EHIP, RX_EBUSY, RX_ENOMEM, RX_EJIT, RX_ETIMEOUT = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+EPS, BYTE, CLASS, CAT, ALT, STAR, PLUS, OPT, PLUSLOOP = range(9)
+RX_SEARCH = 1
+VARIANT_AUTO, VARIANT_LANE, VARIANT_WAVE, VARIANT_SLICED = range(4)
+
+AST_DTYPE = np.dtype(
+    [("kind", np.uint8), ("byte", np.uint8), ("cls", np.uint16), ("c0", np.int32), ("c1", np.int32)]
+)
+
+
+class RxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rx error {code}: {msg}")
+        self.code = code
+
+
+class rx_info(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int32), ("n_leaves", ctypes.c_int32), ("words", ctypes.c_int32),
+        ("nullable", ctypes.c_int32), ("suffix_any", ctypes.c_int32), ("search", ctypes.c_int32),
+        ("table_bytes", ctypes.c_int64), ("depth", ctypes.c_int32), ("n_classes", ctypes.c_int32),
+    ]
+
+
+class rx_node(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("c0", ctypes.c_int32), ("c1", ctypes.c_int32),
+                ("label", ctypes.c_int32), ("cont", ctypes.c_int32)]
+
+
+class rx_launch(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("block", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("unroll", ctypes.c_int32)]
+
+
+_VP, _I32, _I64, _U32, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
+
+# name -> (restype, argtypes); every symbol include/rx.h declares
+SIGNATURES = {
+    "rx_compile": (ctypes.c_int, [_VP, _I32, _I32, _VP, _I32, _U32, ctypes.POINTER(_VP)]),
+    "rx_program_free": (None, [_VP]),
+    "rx_program_info": (ctypes.c_int, [_VP, ctypes.POINTER(rx_info)]),
+    "rx_program_nodes": (ctypes.c_int, [_VP, _VP, _I32, ctypes.POINTER(_I32)]),
+    "rx_program_sets": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "rx_program_upload": (ctypes.c_int, [_VP, _VP, _SZ, _VP]),
+    "rx_match": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _VP]),
+    "rx_match_ex": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, ctypes.POINTER(rx_launch), _VP]),
+    "rx_last_error": (ctypes.c_char_p, []),
+    "rx_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded librx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_1108_3126_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != RX_OK:
+        raise RxError(rc, lib().rx_last_error().decode(errors="replace"))
+    return rc
+
+
+def as_ast(ast) -> np.ndarray:
+    if isinstance(ast, np.ndarray) and ast.dtype == AST_DTYPE:
+        return np.ascontiguousarray(ast)
+    if isinstance(ast, np.ndarray) and ast.dtype.names == AST_DTYPE.names:
+        return np.ascontiguousarray(ast.astype(AST_DTYPE))
+    return np.array([tuple(int(v) for v in a) for a in ast], dtype=AST_DTYPE)
+
+
+def as_classes(classes) -> np.ndarray:
+    if classes is None:
+        return np.zeros((0, 4), np.uint64)
+    if isinstance(classes, np.ndarray) and classes.dtype == np.uint64:
+        return np.ascontiguousarray(classes.reshape(-1, 4))
+    out = np.zeros((len(classes), 4), dtype=np.uint64)
+    for i, c in enumerate(classes):
+        if isinstance(c, int):
+            for w in range(4):
+                out[i, w] = (c >> (64 * w)) & ((1 << 64) - 1)
+        else:
+            for b in c:
+                out[i, b >> 6] |= np.uint64(1) << np.uint64(b & 63)
+    return out
+
+
+def _stream_handle(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Program:
+    """A compiled program (rx_compile) plus, once uploaded, its device tables."""
+
+    def __init__(self, ast, root, classes=None, search=False):
+        a = as_ast(ast)
+        c = as_classes(classes)
+        h = ctypes.c_void_p()
+        _check(lib().rx_compile(a.ctypes.data, len(a), int(root), c.ctypes.data if len(c) else None, len(c),
+                                RX_SEARCH if search else 0, ctypes.byref(h)))
+        self._h = h
+        self._dev_buf = None
+        self.info = rx_info()
+        _check(lib().rx_program_info(h, ctypes.byref(self.info)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.rx_program_free(h)
+            self._h = None
+
+    # -- introspection -------------------------------------------------
+    def nodes(self) -> list:
+        m = ctypes.c_int32()
+        _check(lib().rx_program_nodes(self._h, None, 0, ctypes.byref(m)))
+        arr = (rx_node * m.value)()
+        _check(lib().rx_program_nodes(self._h, arr, m.value, ctypes.byref(m)))
+        return [(n.kind, n.c0, n.c1, n.label, n.cont) for n in arr]
+
+    def sets(self):
+        """(first[W], follow[L, W], bytemask[256, W], leaf_node[L]) as numpy arrays."""
+        W, L = self.info.words, self.info.n_leaves
+        first = np.zeros(W, np.uint32)
+        follow = np.zeros((max(L, 1), W), np.uint32)
+        mask = np.zeros((256, W), np.uint32)
+        leaf = np.zeros(max(L, 1), np.int32)
+        _check(lib().rx_program_sets(self._h, first.ctypes.data, follow.ctypes.data, mask.ctypes.data, leaf.ctypes.data))
+        return first, follow[:L], mask, leaf[:L]
+
+    # -- device -----------------------------------------------------------
+    def upload(self, device=None, stream=None):
+        import torch
+
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        nbytes = int(self.info.table_bytes)
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        off = (-buf.data_ptr()) % 256
+        view = buf[off:off + nbytes]
+        with torch.cuda.device(dev):
+            _check(lib().rx_program_upload(self._h, ctypes.c_void_p(view.data_ptr()), nbytes, _stream_handle(stream)))
+        self._dev_buf = buf
+        return self
+
+
+def compile(ast, root, classes=None, search=False) -> Program:
+    return Program(ast, root, classes, search)
+
+
+def match(prog: Program, data, offsets, out=None, launch=None, stream=None):
+    """Match every string against ``prog``: returns a uint8 tensor of 0/1 on the device."""
+    import torch
+
+    if prog._dev_buf is None:
+        prog.upload(device=data.device if data.numel() else offsets.device, stream=stream)
+    if data.dtype != torch.uint8 or offsets.dtype != torch.int64:
+        raise TypeError("data must be uint8 and offsets int64")
+    if not (data.is_cuda and offsets.is_cuda):
+        raise TypeError("data and offsets must be device tensors")
+    data = data.contiguous()
+    offsets = offsets.contiguous()
+    n = offsets.numel() - 1
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.uint8, device=offsets.device)
+    sh = _stream_handle(stream)
+    dptr = ctypes.c_void_p(data.data_ptr() if data.numel() else offsets.data_ptr())
+    if launch is None:
+        _check(lib().rx_match(prog.handle, dptr, ctypes.c_void_p(offsets.data_ptr()), n,
+                              ctypes.c_void_p(out.data_ptr()), sh))
+    else:
+        L = launch if isinstance(launch, rx_launch) else rx_launch(*launch)
+        _check(lib().rx_match_ex(prog.handle, dptr, ctypes.c_void_p(offsets.data_ptr()), n,
+                                 ctypes.c_void_p(out.data_ptr()), ctypes.byref(L), sh))
+    return out
+
+
+def version() -> str:
+    return lib().rx_version().decode()

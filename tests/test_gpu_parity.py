@@ -1,0 +1,162 @@
+"""GPU parity: the HIP kernels (through the C interface) against the CPU
+oracle, bit for bit, on seeded inputs.  Also determinacy across kernel
+variants and launch shapes (Thm. 7.2: the parallel schedule does not change
+the result) and edge cases."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1108_3126_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+VARIANTS = None
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1108_3126_amd import rx
+
+    global VARIANTS
+    VARIANTS = [rx.VARIANT_LANE, rx.VARIANT_WAVE]
+    return torch.device("cuda:0")
+
+
+def gpu_match(prog, s, dev, variant=0, block=0, grid=0, unroll=0, p=None):
+    from paper_1108_3126_amd import rx
+
+    if p is None:
+        p = rx.compile(prog.ast, prog.root, prog.classes, prog.search).upload(dev)
+    d = torch.from_numpy(s.data if s.data.size else np.zeros(1, np.uint8)).to(dev)
+    o = torch.from_numpy(s.offsets).to(dev)
+    out = rx.match(p, d, o, launch=(variant, block, grid, unroll) if variant or block or grid else None)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def oracle_match(prog, s, index=None):
+    return oracle.match(prog.ast, prog.root, prog.classes, prog.search, s.data, s.offsets, index=index)
+
+
+def test_small_seed0_all_variants(dev):
+    prog = W.small_program(0)
+    s = W.small_strings(0)
+    want = oracle_match(prog, s)
+    print("small seed 0: n", s.n, "accepted", int(want.sum()), flush=True)
+    for v in VARIANTS:
+        assert np.array_equal(gpu_match(prog, s, dev, variant=v), want), v
+
+
+@pytest.mark.parametrize("block", range(0, 300, 50))
+def test_small_fuzz(dev, block):
+    from paper_1108_3126_amd import rx
+
+    for seed in range(block, block + 50):
+        prog = W.small_program(seed)
+        s = W.small_strings(seed)
+        for search in (False, True):
+            prog.search = search
+            want = oracle_match(prog, s)
+            p = rx.compile(prog.ast, prog.root, prog.classes, search).upload(dev)
+            got = gpu_match(prog, s, dev, p=p)
+            assert np.array_equal(got, want), (seed, search, np.nonzero(got != want)[0][:5])
+
+
+def test_single_program_reduced(dev):
+    prog = W.single_program(1)
+    s, planted = W.single_strings(prog, seed=1, n=4096)
+    want = oracle_match(prog, s)
+    assert want[planted].all()
+    print("single reduced: accepted", int(want.sum()), "planted", len(planted), flush=True)
+    for v in VARIANTS:
+        assert np.array_equal(gpu_match(prog, s, dev, variant=v), want), v
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_single_program_other_seeds(dev, seed):
+    prog = W.single_program(seed)
+    s, planted = W.single_strings(prog, seed=seed, n=2048)
+    want = oracle_match(prog, s)
+    assert want[planted].all()
+    assert np.array_equal(gpu_match(prog, s, dev), want)
+
+
+def test_launch_shapes_are_determinate(dev):
+    prog = W.single_program(1)
+    s, _ = W.single_strings(prog, seed=5, n=3000)
+    from paper_1108_3126_amd import rx
+
+    base = gpu_match(prog, s, dev)
+    for v, block, grid in [(rx.VARIANT_LANE, 64, 1), (rx.VARIANT_LANE, 128, 7), (rx.VARIANT_LANE, 256, 0),
+                           (rx.VARIANT_WAVE, 64, 3), (rx.VARIANT_WAVE, 512, 0), (rx.VARIANT_WAVE, 1024, 2)]:
+        assert np.array_equal(gpu_match(prog, s, dev, variant=v, block=block, grid=grid), base), (v, block, grid)
+
+
+def test_edge_cases(dev):
+    from paper_1108_3126_amd import rx
+
+    # (a|b)* c? with classes, empty strings, unaligned offsets, bytes 0 and 255
+    ast = [(rx.BYTE, 97, 0, -1, -1), (rx.CLASS, 0, 0, -1, -1), (rx.ALT, 0, 0, 0, 1), (rx.STAR, 0, 0, 2, -1),
+           (rx.BYTE, 0, 0, -1, -1), (rx.OPT, 0, 0, 4, -1), (rx.CAT, 0, 0, 3, 5)]
+    classes = W.random_classes(np.random.default_rng(9), 1)
+    classes[0] = W.class_words({98, 255})
+    prog = W.Program(np.array(ast, dtype=W.AST_DTYPE), 6, classes, False)
+    strs = [b"", b"a", b"\x00", b"ab\xff\x00", b"ab\xffa\x00\x00", b"x", b"\xff" * 37, b"a" * 17 + b"\x00",
+            b"b" * 15, b"b" * 16, b"b" * 33 + b"\x01"]
+    s = W.pack(strs)
+    for search in (False, True):
+        prog.search = search
+        want = oracle_match(prog, s)
+        for v in VARIANTS:
+            assert np.array_equal(gpu_match(prog, s, dev, variant=v), want), (search, v)
+    # every string empty
+    s0 = W.pack([b""] * 70)
+    prog.search = False
+    want = oracle_match(prog, s0)
+    assert want.all()
+    for v in VARIANTS:
+        assert np.array_equal(gpu_match(prog, s0, dev, variant=v), want)
+    # strings starting at every alignment inside one buffer
+    rng = np.random.default_rng(11)
+    data = rng.choice(np.frombuffer(b"ab\x00\xff", np.uint8), size=4000)
+    cuts = np.sort(rng.integers(0, 4000, size=300))
+    offs = np.concatenate([[0], cuts, [4000]]).astype(np.int64)
+    s1 = W.Strings(data.astype(np.uint8), offs)
+    for search in (False, True):
+        prog.search = search
+        want = oracle_match(prog, s1)
+        for v in VARIANTS:
+            assert np.array_equal(gpu_match(prog, s1, dev, variant=v), want), (search, v)
+
+
+def test_zero_strings_is_noop(dev):
+    from paper_1108_3126_amd import rx
+
+    p = rx.compile([(rx.BYTE, 97, 0, -1, -1)], 0).upload(dev)
+    out = rx.match(p, torch.zeros(1, dtype=torch.uint8, device=dev), torch.zeros(1, dtype=torch.int64, device=dev))
+    assert out.numel() == 0
+
+
+@pytest.mark.parametrize("family,k", [("nested", 1), ("nested", 8), ("nested", 64), ("altstar", 1), ("altstar", 8),
+                                      ("altstar", 64)])
+def test_pathological_small_k(dev, family, k):
+    prog = W.pathological_program(family, k)
+    for n in (1, 2, 100, 1000):
+        s = W.pathological_strings(family, n, count=64)
+        want = oracle_match(prog, s)
+        assert want[:32].sum() == 0 and want[32:].all()  # closed form: a* t
+        assert np.array_equal(gpu_match(prog, s, dev), want), (family, k, n)
+
+
+@pytest.mark.parametrize("family,k", [("nested", 819), ("altstar", 585)])
+def test_pathological_4096_nodes(dev, family, k):
+    prog = W.pathological_program(family, k)
+    s = W.pathological_strings(family, 1000, count=16)
+    print(f"pathological {family} k={k} n=1000", flush=True)
+    want = oracle_match(prog, s)
+    assert want[:8].sum() == 0 and want[8:].all()
+    assert np.array_equal(gpu_match(prog, s, dev), want)
