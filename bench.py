@@ -39,11 +39,15 @@ def main():
     ap.add_argument("--strings", type=int, default=1_000_000)
     ap.add_argument("--length", type=int, default=256)
     ap.add_argument("--copies", type=int, default=4, help="input copies rotated across steps")
-    ap.add_argument("--variant", type=int, default=0, help="kernel variant (0 = library default)")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="kernel variant: 0 = library default (sliced circuit when compiled), 1 lane, 2 wave, 3 sliced")
+    ap.add_argument("--layout", choices=["fixed", "offsets"], default="fixed",
+                    help="fixed: strings of equal length back to back (rx_match_fixed); offsets: rx_match")
+    ap.add_argument("--no-jit", action="store_true", help="do not compile the bit-sliced circuit")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--unroll", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=20000, help="strings the CPU oracle times")
+    ap.add_argument("--cpu-sample", type=int, default=1000000, help="strings the CPU oracle times")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--check", type=int, default=2000, help="sampled strings checked against the oracle")
     args = ap.parse_args()
@@ -68,6 +72,10 @@ def main():
     p = rx.compile(prog.ast, prog.root, prog.classes, search=True).upload(dev)
     info = p.info
     log(f"program: m={info.m} L={info.n_leaves} words={info.words} table_bytes={info.table_bytes}")
+    if not args.no_jit:
+        j0 = time.time()
+        p.jit()
+        log(f"bit-sliced circuit compiled in {time.time() - j0:.2f}s: {p.jit_stats()}")
     offs = torch.from_numpy(strings.offsets).to(dev)
     copies = [torch.from_numpy(strings.data).to(dev)]
     for _ in range(1, max(1, args.copies)):
@@ -78,7 +86,10 @@ def main():
         launch = (args.variant, args.block, args.grid, args.unroll)
 
     def step(i):
-        rx.match(p, copies[i % len(copies)], offs, out=out, launch=launch)
+        if args.layout == "fixed":
+            rx.match_fixed(p, copies[i % len(copies)], args.length, strings.n, out=out, launch=launch)
+        else:
+            rx.match(p, copies[i % len(copies)], offs, out=out, launch=launch)
 
     for i in range(args.warmup):
         step(i)
@@ -110,7 +121,7 @@ def main():
     input_bytes = int(strings.offsets[-1])
     value = input_bytes / (ms_per_step * 1e-3) / 1e9
     avg_kernel_ms = float(np.mean(kern_ms))
-    algo_bytes = input_bytes + 8 * (strings.n + 1) + strings.n
+    algo_bytes = input_bytes + strings.n + (8 * (strings.n + 1) if args.layout == "offsets" else 0)
     achieved = algo_bytes / (avg_kernel_ms * 1e-3) / 1e9
     log(f"kernel ms: mean {avg_kernel_ms:.4f} median {np.median(kern_ms):.4f} min {min(kern_ms):.4f}; "
         f"wall ms/step {ms_per_step:.4f}")
@@ -130,6 +141,8 @@ def main():
         log(f"cpu oracle: {cpu}")
 
     variant_name = {0: "auto", 1: "lane", 2: "wave", 3: "sliced"}[args.variant]
+    if args.variant == 0:
+        variant_name = "sliced" if (args.layout == "fixed" and not args.no_jit) else "lane"
     rec = {
         "metric": "input GB/s scanned (bit-exact)",
         "value": round(value, 3),
@@ -153,6 +166,7 @@ def main():
             "leaves": int(info.n_leaves),
             "kernel": variant_name,
             "input_copies": len(copies),
+            "layout": args.layout,
         },
         "roofline": {
             "bound": "hbm",

@@ -196,6 +196,44 @@ typedef struct {
 int rx_match_ex(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t n,
                 uint8_t* d_out, const rx_launch* launch, void* stream);
 
+/*
+ * Fixed-length strings: string i is d_bytes[i * length .. (i + 1) * length).
+ * No offsets array is read.  With a run-time compiled bit-sliced circuit
+ * (rx_program_jit), a 16-byte aligned d_bytes and length a multiple of 16,
+ * the sliced kernel runs (one lane advances 32 strings per instruction);
+ * otherwise the table-form kernels run.  Same results either way.
+ * Errors: RX_EINVAL, RX_ENOTUPLOADED, RX_EHIP.
+ */
+int rx_match_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int64_t n, uint8_t* d_out,
+                   void* stream);
+
+/* rx_match_fixed with an explicit variant and launch shape (RX_VARIANT_SLICED
+ * requires rx_program_jit, 16-byte alignment and length % 16 == 0). */
+int rx_match_fixed_ex(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int64_t n, uint8_t* d_out,
+                      const rx_launch* launch, void* stream);
+
+/*
+ * Generates the bit-sliced node circuit of the program (the per-node
+ * processes of Section 7 evaluated as boolean signals: one 32-bit word per
+ * node carries 32 strings) and compiles it with hiprtc.  arch: a gfx target
+ * such as "gfx950", or NULL for the current device (then the code object is
+ * also loaded, ready for rx_match_fixed).  Compiling for an explicit arch
+ * without a device only checks that the generated source builds.
+ * Programs whose circuit keeps more than 160 leaf states are refused with
+ * RX_ETOOBIG (they would not fit in registers); the table-form kernels run
+ * them.  Errors: RX_EJIT (message holds the compiler log), RX_ETOOBIG, RX_EHIP.
+ */
+int rx_program_jit(rx_program* prog, const char* arch);
+
+/* Copies the generated circuit source (NUL-terminated) into buf[0 .. cap) and
+ * sets *len to its length without the NUL; buf may be NULL to query *len. */
+int rx_program_jit_source(const rx_program* prog, char* buf, size_t cap, size_t* len);
+
+/* ready: 1 when a loaded sliced kernel exists; state_words: 32-bit words of
+ * live thread state per lane; ops: bitwise operations per byte step before
+ * the device compiler's own simplification. */
+int rx_program_jit_stats(const rx_program* prog, int32_t* ready, int32_t* state_words, int32_t* ops);
+
 /* Thread-local message of the last failed call on this host thread. */
 const char* rx_last_error(void);
 

@@ -41,6 +41,7 @@ int make_launch_args(const Program* P, const uint8_t* d_bytes, const int64_t* d_
     a->suffix_any = P->suffix_any ? 1 : 0;
     a->bytes = d_bytes;
     a->offsets = d_offsets;
+    a->stride = 0;
     a->n = n;
     a->out = d_out;
     a->block = 0;
@@ -86,7 +87,9 @@ int rx_compile(const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx_cla
 
 void rx_program_free(rx_program* prog) {
     try {
-        delete reinterpret_cast<Program*>(prog);
+        Program* P = reinterpret_cast<Program*>(prog);
+        if (P) jit_free(P);
+        delete P;
     } catch (...) {
     }
 }
@@ -191,6 +194,98 @@ int rx_match_ex(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d
 int rx_match(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t n,
              uint8_t* d_out, void* stream) {
     return rx_match_ex(prog, d_bytes, d_offsets, n, d_out, nullptr, stream);
+}
+
+int rx_match_fixed_ex(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int64_t n, uint8_t* d_out,
+                      const rx_launch* launch, void* stream) {
+    RX_GUARD_BEGIN
+    const Program* P = reinterpret_cast<const Program*>(prog);
+    if (length < 0) return fail(RX_EINVAL, "negative length");
+    if (n > 0 && length > 0 && !d_bytes) return fail(RX_EINVAL, "NULL device buffer");
+    LaunchArgs a;
+    // offsets are not read: pass a non-null placeholder through the checks
+    if (int rc = make_launch_args(P, d_bytes ? d_bytes : d_out, reinterpret_cast<const int64_t*>(d_out), n, d_out,
+                                  stream, &a))
+        return rc;
+    if (n == 0) return RX_OK;
+    a.offsets = nullptr;
+    a.stride = length;
+    int variant = launch ? launch->variant : RX_VARIANT_AUTO;
+    if (launch) {
+        if (launch->block < 0 || launch->block > 1024 || (launch->block % 64) != 0)
+            return fail(RX_EINVAL, "block must be a multiple of 64 in [64, 1024]");
+        if (launch->grid < 0) return fail(RX_EINVAL, "negative grid");
+        a.block = launch->block;
+        a.grid = launch->grid;
+        a.unroll = launch->unroll;
+    }
+    const bool sliced_ok = jit_ready(P, nullptr, nullptr) && length > 0 && (length % 16) == 0 &&
+                           (reinterpret_cast<uintptr_t>(d_bytes) & 15) == 0;
+    if (variant == RX_VARIANT_AUTO)
+        variant = sliced_ok ? RX_VARIANT_SLICED : (P->W <= kLaneMaxWords ? RX_VARIANT_LANE : RX_VARIANT_WAVE);
+    int e;
+    switch (variant) {
+    case RX_VARIANT_SLICED:
+        if (!jit_ready(P, nullptr, nullptr)) return fail(RX_EINVAL, "sliced kernel needs rx_program_jit first");
+        if (!sliced_ok) return fail(RX_EINVAL, "sliced kernel needs 16-byte aligned bytes and length % 16 == 0");
+        {
+            int dev = -1;
+            hip_current_device(&dev);
+            e = launch_sliced_fixed(P, d_bytes, length, n, d_out, stream);
+        }
+        break;
+    case RX_VARIANT_LANE:
+        if (P->W > kLaneMaxWords) return fail(RX_ETOOBIG, "the lane kernel holds sets of at most 16 words");
+        if (a.block > 256) return fail(RX_EINVAL, "the lane kernel runs at most 256 threads per workgroup");
+        e = launch_lane(a);
+        break;
+    case RX_VARIANT_WAVE:
+        if (P->W > kWaveMaxWords) return fail(RX_ETOOBIG, "the wavefront kernel holds sets of at most 128 words");
+        e = launch_wave(a);
+        break;
+    default: return fail(RX_EINVAL, "unknown kernel variant");
+    }
+    if (e) return hip_fail(e, "kernel launch");
+    return RX_OK;
+    RX_GUARD_END
+}
+
+int rx_match_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int64_t n, uint8_t* d_out,
+                   void* stream) {
+    return rx_match_fixed_ex(prog, d_bytes, length, n, d_out, nullptr, stream);
+}
+
+int rx_program_jit(rx_program* prog, const char* arch) {
+    RX_GUARD_BEGIN
+    if (!prog) return fail(RX_EINVAL, "program is NULL");
+    int rc = jit_compile(reinterpret_cast<Program*>(prog), arch);
+    if (rc == RX_OK) clear_error();
+    return rc;
+    RX_GUARD_END
+}
+
+int rx_program_jit_source(const rx_program* prog, char* buf, size_t cap, size_t* len) {
+    RX_GUARD_BEGIN
+    if (!prog) return fail(RX_EINVAL, "program is NULL");
+    const std::string s = jit_full_source(*reinterpret_cast<const Program*>(prog), nullptr, nullptr);
+    if (len) *len = s.size();
+    if (buf && cap) {
+        const size_t k = s.size() < cap - 1 ? s.size() : cap - 1;
+        std::memcpy(buf, s.data(), k);
+        buf[k] = 0;
+    }
+    return RX_OK;
+    RX_GUARD_END
+}
+
+int rx_program_jit_stats(const rx_program* prog, int32_t* ready, int32_t* state_words, int32_t* ops) {
+    if (!prog) return fail(RX_EINVAL, "program is NULL");
+    int ns = 0, no = 0;
+    const bool r = jit_ready(reinterpret_cast<const Program*>(prog), &ns, &no);
+    if (ready) *ready = r ? 1 : 0;
+    if (state_words) *state_words = ns;
+    if (ops) *ops = no;
+    return RX_OK;
 }
 
 const char* rx_last_error(void) { return last_error_cstr(); }

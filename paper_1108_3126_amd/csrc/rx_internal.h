@@ -15,6 +15,7 @@ constexpr int kMaxLeaves = 4095;        // accept bit is rank L, so sets hold <=
 constexpr int kMaxNodes = 1 << 20;
 constexpr int kLaneMaxWords = 16;       // one-lane-per-string kernel limit (L <= 511)
 constexpr int kWaveMaxWords = 128;      // wavefront kernel limit: lane j owns words j and j+64
+constexpr int kJitMaxState = 160;       // sliced circuit: leaf state words kept in registers
 
 // Device table layout (all offsets in bytes from the start of the uploaded
 // buffer, each section 256-byte aligned).
@@ -63,13 +64,22 @@ struct LaunchArgs {
     int32_t L, W;
     int32_t suffix_any;
     const uint8_t* bytes;
-    const int64_t* offsets;
+    const int64_t* offsets;  // NULL: fixed-length strings, string i at bytes + i * stride
+    int64_t stride;
     int64_t n;
     uint8_t* out;
     int32_t block, grid, unroll;
     void* stream;
 };
 int launch_lane(const LaunchArgs& a);
+// bit-sliced node circuit (rx_jit.cpp)
+std::string jit_step_source(const Program& P, int* n_state, int* n_ops);
+std::string jit_full_source(const Program& P, int* n_state, int* n_ops);
+int jit_compile(Program* P, const char* arch);
+void jit_free(Program* P);
+bool jit_ready(const Program* P, int* n_state, int* n_ops);
+int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,
+                        void* stream);
 int launch_wave(const LaunchArgs& a);
 const char* hip_error_string(int err);
 int hip_current_device(int* dev);

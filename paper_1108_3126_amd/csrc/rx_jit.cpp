@@ -1,0 +1,450 @@
+// Bit-sliced node circuit: code generation and run-time compilation.
+//
+// The lockstep macro step (Def. 5.2) is evaluated as a boolean circuit over the
+// node tree -- the per-node processes of Section 7 (each node forwards the
+// thread to its children or its continuation; leaves wait for the input byte)
+// with messages as bits.  One 32-bit word per node holds that node's signal for
+// 32 strings at once, so every bitwise instruction advances 32 strings.
+//
+// For one input byte c and current leaf set S (X_x = S_x AND [c in label x]):
+//   bottom-up  out(p): a thread that consumed c inside p's subtree reaches cont p
+//     leaf x        out = X_x
+//     eps           out = 0
+//     cat(a, b)     out = out b  OR (nullable b AND out a)
+//     alt(a, b)     out = out a  OR out b
+//     star/plus/opt out = out a
+//   top-down   in(p): a thread arrives at p during the evolution of this step
+//     root          in = 0           (no thread re-enters the root)
+//     cat(a, b)     in a = in p,  in b = out a OR (nullable a AND in p)
+//     alt(a, b)     in a = in b = in p
+//     star/plus     in a = in p OR out a   (the body loops back, Fig. 4.2)
+//     opt           in a = in p
+//   S'_x = in(x) for every leaf x; the accept bit (null reached) is out(root).
+// Every non-consuming path of Fig. 4.2 is covered by these two passes, so no
+// fixpoint iteration is needed even though cont pointers form cycles
+// (Section 4 notes the cycle through a nested star).  OR-ing signals that
+// arrive at the same node is the removal of duplicate threads by pointer
+// equality.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "rx_internal.h"
+
+namespace rx {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// a tiny expression emitter with constant folding
+// ---------------------------------------------------------------------------
+struct V {
+    int c;          // 0 or 1: constant all-zeros / all-ones; -1: a named value
+    std::string n;  // C expression name when c == -1
+};
+
+struct Emitter {
+    std::ostringstream code;
+    int tmp = 0;
+    int ops = 0;
+    V zero{0, ""}, one{1, ""};
+
+    V def(const std::string& expr) {
+        const std::string name = "t" + std::to_string(tmp++);
+        code << "    const u32 " << name << " = " << expr << ";\n";
+        ++ops;
+        return V{-1, name};
+    }
+    static std::string str(const V& v) {
+        if (v.c == 0) return "0u";
+        if (v.c == 1) return "0xffffffffu";
+        return v.n;
+    }
+    V AND(const V& a, const V& b) {
+        if (a.c == 0 || b.c == 0) return zero;
+        if (a.c == 1) return b;
+        if (b.c == 1) return a;
+        if (a.n == b.n) return a;
+        return def(a.n + " & " + b.n);
+    }
+    V OR(const V& a, const V& b) {
+        if (a.c == 1 || b.c == 1) return one;
+        if (a.c == 0) return b;
+        if (b.c == 0) return a;
+        if (a.n == b.n) return a;
+        return def(a.n + " | " + b.n);
+    }
+    V NOT(const V& a) {
+        if (a.c == 0) return one;
+        if (a.c == 1) return zero;
+        return def("~" + a.n);
+    }
+};
+
+// Bit-sliced membership of the input byte in a byte set, from the eight bit
+// planes b0..b7 (plane k holds bit k of the current byte of 32 strings).
+// Products over three fixed bit groups are shared between labels:
+//   H[h]: bits 7..5 == h,  M[u]: bits 4..2 == u,  Q[v]: bits 1..0 == v.
+struct Decoder {
+    Emitter& E;
+    V H[8], M[8], Q[4];
+    bool hH[8] = {}, hM[8] = {}, hQ[4] = {};
+    explicit Decoder(Emitter& e) : E(e) {}
+
+    V lit(int bit, int val) { return val ? V{-1, "b" + std::to_string(bit)} : V{-1, "nb" + std::to_string(bit)}; }
+    V prod3(int hi_bit, int v) {
+        return E.AND(E.AND(lit(hi_bit, (v >> 2) & 1), lit(hi_bit - 1, (v >> 1) & 1)), lit(hi_bit - 2, v & 1));
+    }
+    V getH(int h) { if (!hH[h]) { H[h] = prod3(7, h); hH[h] = true; } return H[h]; }
+    V getM(int u) { if (!hM[u]) { M[u] = prod3(4, u); hM[u] = true; } return M[u]; }
+    V getQ(int v) {
+        if (!hQ[v]) { Q[v] = E.AND(lit(1, (v >> 1) & 1), lit(0, v & 1)); hQ[v] = true; }
+        return Q[v];
+    }
+    V decode(const std::array<uint64_t, 4>& set) {
+        int cnt = 0;
+        for (int w = 0; w < 4; ++w) cnt += __builtin_popcountll(set[w]);
+        if (cnt == 0) return E.zero;
+        if (cnt == 256) return E.one;
+        if (cnt > 128) {
+            std::array<uint64_t, 4> inv = {~set[0], ~set[1], ~set[2], ~set[3]};
+            return E.NOT(decode(inv));
+        }
+        auto has = [&](int b) { return (set[b >> 6] >> (b & 63)) & 1; };
+        V acc = E.zero;
+        for (int h = 0; h < 8; ++h) {
+            int n_h = 0;
+            for (int b = h * 32; b < h * 32 + 32; ++b) n_h += (int)has(b);
+            if (n_h == 0) continue;
+            V term;
+            if (n_h == 32) {
+                term = getH(h);
+            } else {
+                V inner = E.zero;
+                for (int u = 0; u < 8; ++u) {
+                    const int b0 = h * 32 + u * 4;
+                    int mask = 0;
+                    for (int v = 0; v < 4; ++v) mask |= (int)has(b0 + v) << v;
+                    if (!mask) continue;
+                    V t;
+                    if (mask == 15) {
+                        t = getM(u);
+                    } else {
+                        V g = E.zero;
+                        for (int v = 0; v < 4; ++v)
+                            if (mask >> v & 1) g = E.OR(g, getQ(v));
+                        t = E.AND(getM(u), g);
+                    }
+                    inner = E.OR(inner, t);
+                }
+                term = E.AND(getH(h), inner);
+            }
+            acc = E.OR(acc, term);
+        }
+        return acc;
+    }
+};
+
+bool is_leaf_kind(int k) { return k == RX_BYTE || k == RX_CLASS; }
+
+// The search prefix (any byte)* of RX_SEARCH keeps its leaf live forever:
+// that leaf's state is the constant all-ones.
+int search_prefix_leaf(const Program& P) {
+    if (!(P.flags & RX_SEARCH) || P.kind[0] != RX_CAT) return -1;
+    const int left = P.c0[0];
+    if (left < 0 || P.kind[left] != RX_CAT) return -1;
+    const int pre = P.c0[left];
+    if (pre < 0 || P.kind[pre] != RX_STAR) return -1;
+    const int dot = P.c0[pre];
+    if (dot < 0 || P.kind[dot] != RX_CLASS) return -1;
+    const auto& c = P.classes[P.label[dot]];
+    if ((c[0] & c[1] & c[2] & c[3]) != ~0ull) return -1;
+    return dot;
+}
+
+std::array<uint64_t, 4> label_set(const Program& P, int p) {
+    std::array<uint64_t, 4> s = {0, 0, 0, 0};
+    if (P.kind[p] == RX_BYTE) s[P.label[p] >> 6] |= 1ull << (P.label[p] & 63);
+    else s = P.classes[P.label[p]];
+    return s;
+}
+
+}  // namespace
+
+// Generates the step function (device/host neutral C++): rx_step(s, acc, b0..b7)
+// plus the initial state.  Fills n_state (state words) and n_ops.
+std::string jit_step_source(const Program& P, int* n_state, int* n_ops) {
+    const int nt = P.n_tree;
+    std::vector<char> nu(nt, 0);
+    for (int p = nt - 1; p >= 0; --p) {
+        const int a = P.c0[p], b = P.c1[p];
+        switch (P.kind[p]) {
+        case RX_EPS: nu[p] = 1; break;
+        case RX_BYTE: case RX_CLASS: nu[p] = 0; break;
+        case RX_CAT: nu[p] = nu[a] && nu[b]; break;
+        case RX_ALT: nu[p] = nu[a] || nu[b]; break;
+        case RX_STAR: case RX_OPT: nu[p] = 1; break;
+        case RX_PLUS: nu[p] = nu[a]; break;
+        default: nu[p] = 0; break;
+        }
+    }
+    const int pre = search_prefix_leaf(P);
+    // state slots for leaves other than the constant prefix leaf
+    std::vector<int> slot(P.m, -1);
+    int ns = 0;
+    for (int r = 0; r < P.L; ++r) {
+        const int x = P.leaf_node[r];
+        if (x != pre) slot[x] = ns++;
+    }
+    Emitter E;
+    E.code << "    const u32 nb0 = ~b0, nb1 = ~b1, nb2 = ~b2, nb3 = ~b3, nb4 = ~b4, nb5 = ~b5, nb6 = ~b6, nb7 = ~b7;\n";
+    Decoder D(E);
+    // one decoded mask per distinct label
+    std::vector<std::array<uint64_t, 4>> seen_sets;
+    std::vector<V> seen_vals;
+    std::vector<V> lab(P.m, E.zero);
+    for (int r = 0; r < P.L; ++r) {
+        const int x = P.leaf_node[r];
+        const auto s = label_set(P, x);
+        int found = -1;
+        for (size_t i = 0; i < seen_sets.size(); ++i)
+            if (seen_sets[i] == s) { found = (int)i; break; }
+        if (found < 0) {
+            seen_sets.push_back(s);
+            seen_vals.push_back(D.decode(s));
+            found = (int)seen_vals.size() - 1;
+        }
+        lab[x] = seen_vals[found];
+    }
+    auto state = [&](int x) { return slot[x] < 0 ? E.one : V{-1, "s[" + std::to_string(slot[x]) + "]"}; };
+    std::vector<V> out(nt, E.zero), in(nt, E.zero);
+    for (int p = nt - 1; p >= 0; --p) {
+        const int a = P.c0[p], b = P.c1[p];
+        switch (P.kind[p]) {
+        case RX_BYTE: case RX_CLASS: out[p] = E.AND(state(p), lab[p]); break;
+        case RX_EPS: out[p] = E.zero; break;
+        case RX_CAT: out[p] = E.OR(out[b], nu[b] ? out[a] : E.zero); break;
+        case RX_ALT: out[p] = E.OR(out[a], out[b]); break;
+        case RX_STAR: case RX_PLUS: case RX_OPT: out[p] = out[a]; break;
+        default: break;
+        }
+    }
+    in[0] = E.zero;
+    for (int p = 0; p < nt; ++p) {
+        const int a = P.c0[p], b = P.c1[p];
+        switch (P.kind[p]) {
+        case RX_CAT:
+            in[a] = in[p];
+            in[b] = E.OR(out[a], nu[a] ? in[p] : E.zero);
+            break;
+        case RX_ALT: in[a] = in[p]; in[b] = in[p]; break;
+        case RX_STAR: case RX_PLUS: in[a] = E.OR(in[p], out[a]); break;
+        case RX_OPT: in[a] = in[p]; break;
+        default: break;
+        }
+    }
+    // commit the new state after every value is computed
+    std::ostringstream tail;
+    for (int r = 0; r < P.L; ++r) {
+        const int x = P.leaf_node[r];
+        if (slot[x] < 0) continue;
+        tail << "    s[" << slot[x] << "] = " << Emitter::str(in[x]) << ";\n";
+    }
+    tail << "    acc = " << Emitter::str(out[0]) << ";\n";
+    std::ostringstream src;
+    src << "#define RX_NS " << (ns > 0 ? ns : 1) << "\n";
+    src << "__device__ __forceinline__ void rx_step(u32 (&s)[RX_NS], u32& acc, u32 b0, u32 b1, u32 b2, u32 b3,"
+           " u32 b4, u32 b5, u32 b6, u32 b7) {\n";
+    src << E.code.str() << tail.str() << "}\n";
+    src << "__device__ __forceinline__ void rx_init(u32 (&s)[RX_NS], u32& acc) {\n";
+    for (int k = 0; k < (ns > 0 ? ns : 1); ++k) src << "    s[" << k << "] = 0u;\n";
+    for (int r = 0; r < P.L; ++r) {
+        const int x = P.leaf_node[r];
+        if (slot[x] >= 0 && ((P.first[r >> 5] >> (r & 31)) & 1)) src << "    s[" << slot[x] << "] = 0xffffffffu;\n";
+    }
+    src << "    acc = " << (P.nullable ? "0xffffffffu" : "0u") << ";\n}\n";
+    if (n_state) *n_state = ns;
+    if (n_ops) *n_ops = E.ops;
+    return src.str();
+}
+
+// 32x32 bit transpose: afterwards a[k] bit j == (before) a[j] bit k.
+const char* kTransposeSource = R"(
+__device__ __forceinline__ void rx_transpose32(u32 (&a)[32]) {
+#pragma unroll
+    for (unsigned d = 16, m = 0x0000ffffu; d > 0; d >>= 1, m ^= (m << d)) {
+#pragma unroll
+        for (unsigned j = 0; j < 32; ++j) {
+            if ((j & d) == 0) {
+                const u32 t = ((a[j] >> d) ^ a[j + d]) & m;
+                a[j + d] ^= t;
+                a[j] ^= t << d;
+            }
+        }
+    }
+}
+)";
+
+// Fixed-length strings: string i is bytes[i*length, (i+1)*length).  One
+// wavefront runs 2048 strings: lane l owns bit j of every word for string
+// base + 64 j + l.  32-byte tiles of every string are staged in LDS by
+// asynchronous 16-byte global->LDS loads, then each lane reads 4 bytes of its
+// 32 strings, transposes them into bit planes and runs four macro steps.
+const char* kFixedKernelSource = R"(
+// ---- device kernel ----
+typedef __attribute__((address_space(1))) void rx_gvoid;
+typedef __attribute__((address_space(3))) void rx_lvoid;
+#define RX_WAVE_STRINGS 2048
+#define RX_TILE 32
+
+extern "C" __global__ __launch_bounds__(64, 1) void rx_sliced_fixed(const unsigned char* __restrict__ bytes,
+        long long length, long long n, unsigned char* __restrict__ out) {
+    extern __shared__ u32 rx_tile[];   // RX_WAVE_STRINGS * RX_TILE bytes
+    const int lane = threadIdx.x;
+    const long long base = (long long)blockIdx.x * RX_WAVE_STRINGS;
+    u32 s[RX_NS];
+    u32 acc;
+    rx_init(s, acc);
+    const long long ntiles = (length + RX_TILE - 1) / RX_TILE;
+    for (long long t = 0; t < ntiles; ++t) {
+        const long long off = t * RX_TILE + 16 * (lane & 1);
+        __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the previous tile has been read
+        if (off < length) {
+#pragma unroll 8
+            for (int q = 0; q < RX_WAVE_STRINGS / 32; ++q) {
+                long long sid = base + q * 32 + (lane >> 1);
+                if (sid > n - 1) sid = n - 1;
+                __builtin_amdgcn_global_load_lds((rx_gvoid*)(bytes + sid * length + off),
+                                                 (rx_lvoid*)(rx_tile + q * 256), 16, 0, 0);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the tile has landed
+        const long long left = length - t * RX_TILE;
+        const int np = left < RX_TILE ? (int)left : RX_TILE;
+        for (int pq = 0; pq < np; pq += 4) {
+            u32 w[32];
+#pragma unroll
+            for (int j = 0; j < 32; ++j) w[j] = rx_tile[(j * 64 + lane) * 8 + (pq >> 2)];
+            rx_transpose32(w);
+            rx_step(s, acc, w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7]);
+            if (pq + 1 < np) rx_step(s, acc, w[8], w[9], w[10], w[11], w[12], w[13], w[14], w[15]);
+            if (pq + 2 < np) rx_step(s, acc, w[16], w[17], w[18], w[19], w[20], w[21], w[22], w[23]);
+            if (pq + 3 < np) rx_step(s, acc, w[24], w[25], w[26], w[27], w[28], w[29], w[30], w[31]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        const long long sid = base + j * 64 + lane;
+        if (sid < n) out[sid] = (unsigned char)((acc >> j) & 1u);
+    }
+}
+)";
+
+struct JitKernel {
+    hipModule_t mod = nullptr;
+    hipFunction_t fixed = nullptr;
+    int dev = -1;
+    int n_state = 0, n_ops = 0;
+    std::string arch;
+};
+
+std::string jit_full_source(const Program& P, int* n_state, int* n_ops) {
+    std::ostringstream s;
+    s << "typedef unsigned int u32;\n";
+    s << jit_step_source(P, n_state, n_ops);
+    s << kTransposeSource;
+    s << kFixedKernelSource;
+    return s.str();
+}
+
+int jit_compile(Program* P, const char* arch_in) {
+    int ns = 0, nops = 0;
+    const std::string src = jit_full_source(*P, &ns, &nops);
+    if (ns > kJitMaxState)
+        return fail(RX_ETOOBIG, "the bit-sliced circuit keeps at most " + std::to_string(kJitMaxState) +
+                                    " state words in registers; this program needs " + std::to_string(ns));
+    std::string arch;
+    int dev = -1;
+    if (arch_in && *arch_in) {
+        arch = arch_in;
+    } else {
+        if (hipGetDevice(&dev) != hipSuccess) return fail(RX_EHIP, "hipGetDevice failed");
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(RX_EHIP, "hipGetDeviceProperties failed");
+        arch = prop.gcnArchName;
+    }
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "rx_sliced.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+        return fail(RX_EJIT, "hiprtcCreateProgram failed");
+    const std::string arch_opt = "--gpu-architecture=" + arch;
+    const char* opts[] = {arch_opt.c_str(), "-O3", "-std=c++17"};
+    const hiprtcResult rc = hiprtcCompileProgram(prog, 3, opts);
+    if (rc != HIPRTC_SUCCESS) {
+        size_t n = 0;
+        hiprtcGetProgramLogSize(prog, &n);
+        std::string log(n, '\0');
+        if (n) hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        return fail(RX_EJIT, "hiprtc compile failed: " + log.substr(0, 2000));
+    }
+    size_t code_size = 0;
+    hiprtcGetCodeSize(prog, &code_size);
+    std::vector<char> code(code_size);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    JitKernel* K = new JitKernel;
+    K->arch = arch;
+    K->n_state = ns;
+    K->n_ops = nops;
+    if (dev >= 0) {
+        hipError_t e = hipModuleLoadData(&K->mod, code.data());
+        if (e != hipSuccess) { delete K; return fail(RX_EHIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e)); }
+        e = hipModuleGetFunction(&K->fixed, K->mod, "rx_sliced_fixed");
+        if (e != hipSuccess) {
+            hipModuleUnload(K->mod);
+            delete K;
+            return fail(RX_EHIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));
+        }
+        K->dev = dev;
+    }
+    if (P->jit) jit_free(P);
+    P->jit = K;
+    return RX_OK;
+}
+
+void jit_free(Program* P) {
+    JitKernel* K = static_cast<JitKernel*>(P->jit);
+    if (!K) return;
+    if (K->mod) hipModuleUnload(K->mod);
+    delete K;
+    P->jit = nullptr;
+}
+
+bool jit_ready(const Program* P, int* n_state, int* n_ops) {
+    const JitKernel* K = static_cast<const JitKernel*>(P->jit);
+    if (n_state) *n_state = K ? K->n_state : 0;
+    if (n_ops) *n_ops = K ? K->n_ops : 0;
+    return K && K->fixed;
+}
+
+int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,
+                        void* stream) {
+    const JitKernel* K = static_cast<const JitKernel*>(P->jit);
+    if (!K || !K->fixed) return (int)hipErrorInvalidValue;
+    const long long grid = (n + 2047) / 2048;
+    const unsigned lds = 2048 * 32;
+    long long len = length, nn = n;
+    const void* b = bytes;
+    void* o = out;
+    void* args[] = {&b, &len, &nn, &o};
+    return (int)hipModuleLaunchKernel(K->fixed, (unsigned)grid, 1, 1, 64, 1, 1, lds, (hipStream_t)stream, args, nullptr);
+}
+
+}  // namespace rx

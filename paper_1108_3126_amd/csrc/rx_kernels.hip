@@ -34,7 +34,8 @@ struct KArgs {
     const uint32_t* bytemask;
     int32_t L, W, suffix_any, pad;
     const uint8_t* bytes;
-    const int64_t* offsets;
+    const int64_t* offsets;  // NULL: string i is bytes[i * stride, (i + 1) * stride)
+    int64_t stride;
     int64_t n;
     uint8_t* out;
 };
@@ -84,7 +85,8 @@ __global__ __launch_bounds__(256) void k_lane(KArgs a) {
         uint32_t S[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) S[w] = a.first[w];
-        const int64_t lo = a.offsets[sid], hi = a.offsets[sid + 1];
+        const int64_t lo = a.offsets ? a.offsets[sid] : sid * a.stride;
+        const int64_t hi = a.offsets ? a.offsets[sid + 1] : lo + a.stride;
         int res = -1;
         // aligned 16-byte blocks of the absolute address range [bytes+lo, bytes+hi):
         // every block read holds at least one byte of the string
@@ -134,7 +136,8 @@ __global__ __launch_bounds__(1024) void k_wave(KArgs a) {
     for (int64_t sid = (int64_t)blockIdx.x * waves + wave; sid < a.n; sid += (int64_t)gridDim.x * waves) {
         uint32_t S0 = own0 ? a.first[lane] : 0u;
         uint32_t S1 = own1 ? a.first[lane + 64] : 0u;
-        const int64_t lo = a.offsets[sid], hi = a.offsets[sid + 1];
+        const int64_t lo = a.offsets ? a.offsets[sid] : sid * a.stride;
+        const int64_t hi = a.offsets ? a.offsets[sid + 1] : lo + a.stride;
         int res = -1;
         const int64_t skew = (int64_t)(reinterpret_cast<uintptr_t>(a.bytes) & 3);
         for (int64_t base = ((lo + skew) & ~int64_t(3)) - skew; base < hi && res < 0; base += 4) {
@@ -191,6 +194,7 @@ KArgs kargs(const LaunchArgs& a) {
     k.pad = 0;
     k.bytes = a.bytes;
     k.offsets = a.offsets;
+    k.stride = a.stride;
     k.n = a.n;
     k.out = a.out;
     return k;

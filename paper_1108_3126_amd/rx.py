@@ -63,6 +63,11 @@ SIGNATURES = {
     "rx_program_upload": (ctypes.c_int, [_VP, _VP, _SZ, _VP]),
     "rx_match": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _VP]),
     "rx_match_ex": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, ctypes.POINTER(rx_launch), _VP]),
+    "rx_match_fixed": (ctypes.c_int, [_VP, _VP, _I64, _I64, _VP, _VP]),
+    "rx_match_fixed_ex": (ctypes.c_int, [_VP, _VP, _I64, _I64, _VP, ctypes.POINTER(rx_launch), _VP]),
+    "rx_program_jit": (ctypes.c_int, [_VP, ctypes.c_char_p]),
+    "rx_program_jit_source": (ctypes.c_int, [_VP, ctypes.c_char_p, _SZ, ctypes.POINTER(_SZ)]),
+    "rx_program_jit_stats": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "rx_last_error": (ctypes.c_char_p, []),
     "rx_version": (ctypes.c_char_p, []),
 }
@@ -164,6 +169,24 @@ class Program:
         _check(lib().rx_program_sets(self._h, first.ctypes.data, follow.ctypes.data, mask.ctypes.data, leaf.ctypes.data))
         return first, follow[:L], mask, leaf[:L]
 
+    # -- bit-sliced circuit -------------------------------------------------
+    def jit(self, arch=None):
+        """Generate and compile the bit-sliced circuit kernel (hiprtc)."""
+        _check(lib().rx_program_jit(self._h, arch.encode() if arch else None))
+        return self
+
+    def jit_source(self) -> str:
+        n = ctypes.c_size_t()
+        _check(lib().rx_program_jit_source(self._h, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value + 1)
+        _check(lib().rx_program_jit_source(self._h, buf, n.value + 1, ctypes.byref(n)))
+        return buf.value.decode()
+
+    def jit_stats(self):
+        r, s, o = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().rx_program_jit_stats(self._h, ctypes.byref(r), ctypes.byref(s), ctypes.byref(o)))
+        return {"ready": r.value, "state_words": s.value, "ops": o.value}
+
     # -- device -----------------------------------------------------------
     def upload(self, device=None, stream=None):
         import torch
@@ -207,6 +230,32 @@ def match(prog: Program, data, offsets, out=None, launch=None, stream=None):
         L = launch if isinstance(launch, rx_launch) else rx_launch(*launch)
         _check(lib().rx_match_ex(prog.handle, dptr, ctypes.c_void_p(offsets.data_ptr()), n,
                                  ctypes.c_void_p(out.data_ptr()), ctypes.byref(L), sh))
+    return out
+
+
+def match_fixed(prog: Program, data, length: int, n: int = None, out=None, launch=None, stream=None):
+    """Match n fixed-length strings (string i = data[i*length:(i+1)*length])."""
+    import torch
+
+    if prog._dev_buf is None:
+        prog.upload(device=data.device, stream=stream)
+    if data.dtype != torch.uint8 or not data.is_cuda:
+        raise TypeError("data must be a uint8 device tensor")
+    data = data.contiguous()
+    if n is None:
+        n = data.numel() // length if length else 0
+    if n * length > data.numel():
+        raise ValueError("data holds fewer than n * length bytes")
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.uint8, device=data.device)
+    sh = _stream_handle(stream)
+    if launch is None:
+        _check(lib().rx_match_fixed(prog.handle, ctypes.c_void_p(data.data_ptr()), int(length), int(n),
+                                    ctypes.c_void_p(out.data_ptr()), sh))
+    else:
+        L = launch if isinstance(launch, rx_launch) else rx_launch(*launch)
+        _check(lib().rx_match_fixed_ex(prog.handle, ctypes.c_void_p(data.data_ptr()), int(length), int(n),
+                                       ctypes.c_void_p(out.data_ptr()), ctypes.byref(L), sh))
     return out
 
 

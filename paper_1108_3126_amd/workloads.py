@@ -215,38 +215,59 @@ def random_tree(rng, n_nodes: int, leaf_byte, n_classes: int, p_class: float,
     return b, root, empty
 
 
-def sample_member(prog: Program, rng, max_len: int = 256, cap_rep: int = 4):
+class _Uniforms:
+    """Uniform [0, 1) draws served from bulk numpy blocks (fast in Python loops)."""
+
+    def __init__(self, rng, block: int = 1 << 16):
+        self.rng, self.block = rng, block
+        self.buf, self.i = rng.random(block).tolist(), 0
+
+    def __call__(self) -> float:
+        if self.i == len(self.buf):
+            self.buf, self.i = self.rng.random(self.block).tolist(), 0
+        u = self.buf[self.i]
+        self.i += 1
+        return u
+
+
+def sample_member(prog: Program, rng, max_len: int = 256, cap_rep: int = 4, _cache=None):
     """A random string of the expression's language by a random derivation:
     alternation uniform, star/plus repetitions geometric(1/2) capped at
     ``cap_rep``, optional a fair coin, classes a uniform member.  Returns None
-    when the draw exceeds ``max_len``."""
-    ast = prog.ast
-    members = {}
+    when the draw exceeds ``max_len``.  ``rng`` is a numpy Generator or a
+    ``_Uniforms`` stream."""
+    u = rng if isinstance(rng, _Uniforms) else _Uniforms(rng, 1024)
+    if _cache is None:
+        _cache = {}
+    if "nodes" not in _cache:
+        _cache["nodes"] = [tuple(int(v) for v in a) for a in prog.ast]
+        _cache["members"] = [class_members(c) for c in prog.classes]
+    nodes, members = _cache["nodes"], _cache["members"]
     out = bytearray()
     work = [int(prog.root)]
     while work:
         p = work.pop()
         if len(out) > max_len:
             return None
-        k, byte, cls, c0, c1 = (int(v) for v in ast[p])
+        k, byte, cls, c0, c1 = nodes[p]
         if k == BYTE:
             out.append(byte)
         elif k == CLASS:
-            if cls not in members:
-                members[cls] = class_members(prog.classes[cls])
             mem = members[cls]
-            out.append(mem[int(rng.integers(0, len(mem)))])
+            out.append(mem[int(u() * len(mem))])
         elif k == CAT:
             work += [c1, c0]
         elif k == ALT:
-            work.append(c0 if rng.random() < 0.5 else c1)
+            work.append(c0 if u() < 0.5 else c1)
         elif k in (STAR, PLUS):
-            reps = min(int(rng.geometric(0.5)) - 1, cap_rep)
+            reps = 0
+            while reps < cap_rep and u() < 0.5:
+                reps += 1
             if k == PLUS:
                 reps = max(reps, 1)
             work += [c0] * reps
         elif k == OPT:
-            if rng.random() < 0.5:
+            if u() < 0.5:
                 work.append(c0)
     return bytes(out) if len(out) <= max_len else None
 
@@ -272,12 +293,14 @@ def single_strings(prog: Program, seed: int = 1, n: int = 1_000_000, length: int
     offs = np.arange(n + 1, dtype=np.int64) * length
     n_plant = int(round(n * plant_frac))
     planted = np.sort(rng.choice(n, size=n_plant, replace=False)) if n_plant else np.zeros(0, np.int64)
+    u = _Uniforms(rng)
+    cache = {}
     for i in planted:
         while True:
-            w = sample_member(prog, rng, max_len=length)
+            w = sample_member(prog, u, max_len=length, _cache=cache)
             if w is not None:
                 break
-        at = int(rng.integers(0, length - len(w) + 1))
+        at = int(u() * (length - len(w) + 1))
         base = int(i) * length + at
         data[base : base + len(w)] = np.frombuffer(w, np.uint8)
     return Strings(data, offs), planted.astype(np.int64)

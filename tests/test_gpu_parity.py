@@ -160,3 +160,73 @@ def test_pathological_4096_nodes(dev, family, k):
     want = oracle_match(prog, s)
     assert want[:8].sum() == 0 and want[8:].all()
     assert np.array_equal(gpu_match(prog, s, dev), want)
+
+
+# ---------------------------------------------------------------------------
+# bit-sliced circuit kernel (fixed-length strings)
+# ---------------------------------------------------------------------------
+def fixed_match(p, s, length, dev, variant=0):
+    from paper_1108_3126_amd import rx
+
+    d = torch.from_numpy(s.data if s.data.size else np.zeros(16, np.uint8)).to(dev)
+    out = rx.match_fixed(p, d, length, s.n, launch=(variant, 0, 0, 0) if variant else None)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_sliced_single_program(dev):
+    from paper_1108_3126_amd import rx
+
+    prog = W.single_program(1)
+    s, planted = W.single_strings(prog, seed=21, n=5000, length=256)
+    p = rx.compile(prog.ast, prog.root, prog.classes, True).upload(dev).jit()
+    assert p.jit_stats()["ready"] == 1
+    want = oracle_match(prog, s)
+    print("sliced single: accepted", int(want.sum()), flush=True)
+    for v in (rx.VARIANT_SLICED, rx.VARIANT_LANE, rx.VARIANT_WAVE, 0):
+        assert np.array_equal(fixed_match(p, s, 256, dev, v), want), v
+
+
+@pytest.mark.parametrize("length", [16, 32, 48, 80, 272])
+def test_sliced_lengths_and_counts(dev, length):
+    from paper_1108_3126_amd import rx
+
+    rng = np.random.default_rng(length)
+    prog = W.single_program(3)
+    for n in (1, 31, 33, 2047, 2049, 4100):
+        s, _ = W.single_strings(prog, seed=length + n, n=n, length=length, plant_frac=0.3)
+        p = rx.compile(prog.ast, prog.root, prog.classes, True).upload(dev).jit()
+        want = oracle_match(prog, s)
+        assert np.array_equal(fixed_match(p, s, length, dev, rx.VARIANT_SLICED), want), (length, n)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_sliced_small_programs(dev, seed):
+    from paper_1108_3126_amd import rx
+
+    rng = np.random.default_rng(seed)
+    for k in range(5):
+        prog = W.small_program(100 + seed * 5 + k)
+        for search in (False, True):
+            p = rx.compile(prog.ast, prog.root, prog.classes, search).upload(dev).jit()
+            data = np.frombuffer(b"ab", np.uint8)[rng.integers(0, 2, size=3000 * 32)].astype(np.uint8)
+            s = W.Strings(data, np.arange(3001, dtype=np.int64) * 32)
+            prog.search = search
+            want = oracle_match(prog, s)
+            assert np.array_equal(fixed_match(p, s, 32, dev, rx.VARIANT_SLICED), want), (seed, k, search)
+
+
+def test_sliced_pathological(dev):
+    from paper_1108_3126_amd import rx
+
+    for family, k in (("nested", 40), ("altstar", 30)):
+        prog = W.pathological_program(family, k)
+        s = W.pathological_strings(family, 1008, count=64)
+        p = rx.compile(prog.ast, prog.root).upload(dev).jit()
+        want = oracle_match(prog, s)
+        assert want[:32].sum() == 0 and want[32:].all()
+        assert np.array_equal(fixed_match(p, s, 1008, dev, rx.VARIANT_SLICED), want), family
+    big = W.pathological_program("altstar", 585)
+    with pytest.raises(rx.RxError) as ei:
+        rx.compile(big.ast, big.root).jit()
+    assert ei.value.code == rx.RX_ETOOBIG
