@@ -234,6 +234,36 @@ int rx_program_jit_source(const rx_program* prog, char* buf, size_t cap, size_t*
  * the device compiler's own simplification. */
 int rx_program_jit_stats(const rx_program* prog, int32_t* ready, int32_t* state_words, int32_t* ops);
 
+/* Length bucketing and launch shape of rx_match_multi; zero fields mean default. */
+typedef struct {
+    int32_t n_edges;    /* bucket edges in use (0 = default ladder 8, 16, 32, ..., 4096) */
+    int32_t edges[15];  /* ascending; bucket b holds lengths in (edges[b-1], edges[b]], the last one the rest */
+    int32_t block;      /* strings per work item = threads per workgroup: 64, 128 or 256 (default 256) */
+    int32_t grid;       /* persistent workgroups (default 4 per compute unit) */
+} rx_multi_config;
+
+/* Device workspace rx_match_multi needs for n strings and n_progs programs
+ * (bytes), or a negative RX_E* code. */
+int64_t rx_match_multi_workspace(int64_t n, int32_t n_progs, const rx_multi_config* cfg);
+
+/*
+ * Batched matching: every string against every program in one persistent
+ * launch (the generic lockstep machine of Def. 5.3 per (program, string)).
+ * Strings are bucketed by length on the device; work items of up to `block`
+ * strings of one bucket against one program are generated on the device,
+ * longest bucket first, and pulled by a persistent kernel from an atomic
+ * queue.  d_out is n_progs x n bytes, row p for program p.  d_work is caller
+ * memory of at least rx_match_multi_workspace(...) bytes, 256-byte aligned; its
+ * contents are scratch (cleared by the call's own kernels, never by a memset).
+ * Programs must be uploaded, hold sets of at most 16 words, and number at
+ * most 64.  Allocates nothing; asynchronous on `stream`.  Results do not
+ * depend on the bucketing or launch shape.
+ * Errors: RX_EINVAL, RX_ETOOBIG, RX_ENOTUPLOADED, RX_EHIP.
+ */
+int rx_match_multi(const rx_program* const* progs, int32_t n_progs, const uint8_t* d_bytes,
+                   const int64_t* d_offsets, int64_t n, uint8_t* d_out, void* d_work, size_t work_bytes,
+                   const rx_multi_config* cfg, void* stream);
+
 /* Thread-local message of the last failed call on this host thread. */
 const char* rx_last_error(void);
 

@@ -255,6 +255,86 @@ int rx_match_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t lengt
     return rx_match_fixed_ex(prog, d_bytes, length, n, d_out, nullptr, stream);
 }
 
+static int multi_shape(const rx_multi_config* cfg, int32_t* edges, int32_t* n_edges, int32_t* block, int32_t* grid) {
+    *n_edges = 0;
+    if (cfg && cfg->n_edges > 0) {
+        if (cfg->n_edges > 15) return fail(RX_EINVAL, "at most 15 bucket edges");
+        for (int i = 0; i < cfg->n_edges; ++i) {
+            if (cfg->edges[i] < 0 || (i > 0 && cfg->edges[i] <= cfg->edges[i - 1]))
+                return fail(RX_EINVAL, "bucket edges must be non-negative and ascending");
+            edges[i] = cfg->edges[i];
+        }
+        *n_edges = cfg->n_edges;
+    } else {
+        for (int e = 8; e <= 4096; e *= 2) edges[(*n_edges)++] = e;
+    }
+    *block = cfg && cfg->block ? cfg->block : 256;
+    if (*block != 64 && *block != 128 && *block != 256) return fail(RX_EINVAL, "block must be 64, 128 or 256");
+    *grid = cfg && cfg->grid > 0 ? cfg->grid : 0;
+    if (cfg && cfg->grid < 0) return fail(RX_EINVAL, "negative grid");
+    if (*grid == 0) {
+        int cus = 0;
+        if (hip_cu_count(&cus) || cus <= 0) cus = 256;
+        *grid = 4 * cus;
+    }
+    return RX_OK;
+}
+
+int64_t rx_match_multi_workspace(int64_t n, int32_t n_progs, const rx_multi_config* cfg) {
+    RX_GUARD_BEGIN
+    if (n < 0 || n_progs < 0) return fail(RX_EINVAL, "negative size");
+    int32_t edges[16], ne, block, grid;
+    if (cfg && cfg->n_edges > 15) return fail(RX_EINVAL, "at most 15 bucket edges");
+    ne = cfg && cfg->n_edges > 0 ? cfg->n_edges : 10;
+    block = cfg && cfg->block ? cfg->block : 256;
+    (void)edges;
+    (void)grid;
+    return multi_workspace_bytes(n, n_progs > 0 ? n_progs : 1, ne + 1, block);
+    RX_GUARD_END
+}
+
+int rx_match_multi(const rx_program* const* progs, int32_t n_progs, const uint8_t* d_bytes,
+                   const int64_t* d_offsets, int64_t n, uint8_t* d_out, void* d_work, size_t work_bytes,
+                   const rx_multi_config* cfg, void* stream) {
+    RX_GUARD_BEGIN
+    if (n_progs <= 0 || !progs) return fail(RX_EINVAL, "no programs");
+    if (n_progs > kMaxItemProgs) return fail(RX_ETOOBIG, "at most 64 programs per call");
+    if (n < 0) return fail(RX_EINVAL, "negative string count");
+    if (n > ((int64_t)1 << 31) - 1) return fail(RX_ETOOBIG, "at most 2^31 - 1 strings per call");
+    if (n > 0 && (!d_bytes || !d_offsets || !d_out)) return fail(RX_EINVAL, "NULL device buffer");
+    if (!d_work || (reinterpret_cast<uintptr_t>(d_work) & 255)) return fail(RX_EINVAL, "workspace must be 256-byte aligned");
+    MultiArgs m;
+    if (int rc = multi_shape(cfg, m.edges, &m.n_edges, &m.block_lines, &m.grid)) return rc;
+    const int64_t need = multi_workspace_bytes(n, n_progs, m.n_edges + 1, m.block_lines);
+    if ((int64_t)work_bytes < need)
+        return fail(RX_ETOOBIG, "workspace holds " + std::to_string(work_bytes) + " bytes; need " + std::to_string(need));
+    for (int i = 0; i < n_progs; ++i) {
+        const Program* P = reinterpret_cast<const Program*>(progs[i]);
+        if (!P) return fail(RX_EINVAL, "program " + std::to_string(i) + " is NULL");
+        if (!P->dev) return fail(RX_ENOTUPLOADED, "program " + std::to_string(i) + " has not been uploaded");
+        if (P->W > kLaneMaxWords) return fail(RX_ETOOBIG, "program " + std::to_string(i) + " holds more than 16 words");
+        const uint8_t* base = static_cast<const uint8_t*>(P->dev);
+        m.progs[i].first = reinterpret_cast<const uint32_t*>(base + P->layout.first);
+        m.progs[i].follow = reinterpret_cast<const uint32_t*>(base + P->layout.follow);
+        m.progs[i].bytemask = reinterpret_cast<const uint32_t*>(base + P->layout.bytemask);
+        m.progs[i].L = P->L;
+        m.progs[i].W = P->W;
+        m.progs[i].suffix_any = P->suffix_any ? 1 : 0;
+        m.progs[i].pad = 0;
+    }
+    m.n_progs = n_progs;
+    m.bytes = d_bytes;
+    m.offsets = d_offsets;
+    m.n = n;
+    m.out = d_out;
+    m.work = d_work;
+    m.stream = stream;
+    if (n == 0) return RX_OK;
+    if (int e = launch_multi(m)) return hip_fail(e, "batched launch");
+    return RX_OK;
+    RX_GUARD_END
+}
+
 int rx_program_jit(rx_program* prog, const char* arch) {
     RX_GUARD_BEGIN
     if (!prog) return fail(RX_EINVAL, "program is NULL");

@@ -47,6 +47,56 @@ struct Program {
     void* jit = nullptr;
 };
 
+// batched matching (rx_multi.hip)
+constexpr int kMaxItemProgs = 64;   // programs per batched launch (descriptors travel as kernel arguments)
+constexpr int kMaxBuckets = 16;     // length bucket edges
+
+struct ProgDesc {                   // device tables of one program
+    const uint32_t* first;
+    const uint32_t* follow;
+    const uint32_t* bytemask;
+    int32_t L, W, suffix_any, pad;
+};
+
+struct WorkItem {                   // up to `block` strings against one program
+    int32_t prog;                   // index into the launch's program descriptors
+    int32_t count;                  // strings in the item
+    int64_t line0;                  // first string (or first entry of the id list)
+    int64_t out0;                   // result of string s goes to out[out0 + s]
+};
+
+struct MultiArgs {
+    ProgDesc progs[kMaxItemProgs];
+    int32_t n_progs;
+    int32_t edges[kMaxBuckets];
+    int32_t n_edges;
+    int32_t block_lines;
+    int32_t grid;
+    const uint8_t* bytes;
+    const int64_t* offsets;
+    int64_t n;
+    uint8_t* out;
+    void* work;
+    void* stream;
+};
+
+struct ItemsArgs {
+    ProgDesc progs[kMaxItemProgs];
+    int32_t n_progs;
+    int32_t block, grid;
+    const uint8_t* bytes;
+    const int64_t* offsets;
+    const WorkItem* items;
+    const int32_t* n_items;
+    int32_t* head;
+    uint8_t* out;
+    void* stream;
+};
+
+int64_t multi_workspace_bytes(int64_t n, int32_t n_progs, int32_t n_buckets, int32_t block_lines);
+int launch_multi(const MultiArgs& m);
+int launch_items(const ItemsArgs& m);
+
 // error reporting (thread-local message)
 int fail(int code, const std::string& msg);
 void clear_error();

@@ -275,17 +275,36 @@ std::string jit_step_source(const Program& P, int* n_state, int* n_ops) {
     return src.str();
 }
 
-// 32x32 bit transpose: afterwards a[k] bit j == (before) a[j] bit k.
+// 32x32 bit transpose: afterwards a[k] bit j == (before) a[j] bit k.  The two
+// byte-granular stages are byte permutes (v_perm_b32, one instruction per
+// word); the three bit stages are a shift plus a bit-field insert per word.
 const char* kTransposeSource = R"(
+#ifndef RX_PERM
+#define RX_PERM(hi, lo, sel) __builtin_amdgcn_perm((hi), (lo), (sel))
+#endif
 __device__ __forceinline__ void rx_transpose32(u32 (&a)[32]) {
 #pragma unroll
-    for (unsigned d = 16, m = 0x0000ffffu; d > 0; d >>= 1, m ^= (m << d)) {
+    for (int j = 0; j < 16; ++j) {
+        const u32 x = a[j], y = a[j + 16];
+        a[j] = RX_PERM(y, x, 0x05040100u);
+        a[j + 16] = RX_PERM(y, x, 0x07060302u);
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        if ((j & 8) == 0) {
+            const u32 x = a[j], y = a[j + 8];
+            a[j] = RX_PERM(y, x, 0x06020400u);
+            a[j + 8] = RX_PERM(y, x, 0x07030501u);
+        }
+    }
+#pragma unroll
+    for (unsigned d = 4, m = 0x0f0f0f0fu; d > 0; d >>= 1, m ^= (m << d)) {
 #pragma unroll
         for (unsigned j = 0; j < 32; ++j) {
             if ((j & d) == 0) {
-                const u32 t = ((a[j] >> d) ^ a[j + d]) & m;
-                a[j + d] ^= t;
-                a[j] ^= t << d;
+                const u32 x = a[j], y = a[j + d];
+                a[j] = (x & m) | ((y << d) & ~m);
+                a[j + d] = ((x >> d) & m) | (y & ~m);
             }
         }
     }

@@ -1,0 +1,294 @@
+// Batched matching: many programs and strings of uneven length in one
+// persistent launch.
+//
+// Strings are bucketed by length on the device (a histogram, a scan over the
+// buckets, a scatter of string ids), so a work item -- up to `block` strings of
+// one bucket against one program -- keeps the lanes of a workgroup busy for a
+// similar number of bytes.  Work items are generated on the device, longest
+// bucket first, and a persistent kernel pulls them from an atomic queue; each
+// workgroup stages the item's program tables in LDS (Def. 5.1 evolutions and
+// byte masks) and runs the table-form macro step of Def. 5.2 with one lane
+// per string.  The same item kernel serves the request batches of the server,
+// whose items name a program and a contiguous range of strings.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "rx_internal.h"
+
+namespace rx {
+
+namespace {
+
+constexpr int kWMax = kLaneMaxWords;
+
+struct ItemKArgs {
+    ProgDesc progs[kMaxItemProgs];
+    int32_t n_progs;
+    int32_t block_lines;
+    const uint8_t* bytes;
+    const int64_t* offsets;
+    const int32_t* ids;     // optional: item lines index this array
+    const WorkItem* items;
+    const int32_t* n_items; // device count
+    int32_t* head;          // device queue head
+    uint8_t* out;
+};
+
+__device__ __forceinline__ void step_rt(uint32_t (&S)[kWMax], int W, uint32_t c, const uint32_t* __restrict__ M,
+                                        const uint32_t* __restrict__ F) {
+    uint32_t X[kWMax];
+#pragma unroll
+    for (int w = 0; w < kWMax; ++w) X[w] = w < W ? (S[w] & M[c * W + w]) : 0u;
+#pragma unroll
+    for (int w = 0; w < kWMax; ++w) S[w] = 0;
+#pragma unroll
+    for (int w = 0; w < kWMax; ++w) {
+        uint32_t x = X[w];
+        while (x) {
+            const int b = __builtin_ctz(x);
+            x &= x - 1;
+            const uint32_t* row = F + (w * 32 + b) * W;
+#pragma unroll
+            for (int v = 0; v < kWMax; ++v)
+                if (v < W) S[v] |= row[v];
+        }
+    }
+}
+
+__device__ int match_one(const uint32_t* __restrict__ first, const uint32_t* M, const uint32_t* F, int L, int W,
+                         int suffix_any, const uint8_t* __restrict__ bytes, int64_t lo, int64_t hi) {
+    uint32_t S[kWMax];
+#pragma unroll
+    for (int w = 0; w < kWMax; ++w) S[w] = w < W ? first[w] : 0u;
+    const int aw = L >> 5;
+    const uint32_t abit = 1u << (L & 31);
+    const int64_t skew = (int64_t)(reinterpret_cast<uintptr_t>(bytes) & 15);
+    for (int64_t base = ((lo + skew) & ~int64_t(15)) - skew; base < hi; base += 16) {
+        const uint4 v = *reinterpret_cast<const uint4*>(bytes + base);
+        const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+        const int b0 = lo > base ? (int)(lo - base) : 0;
+        const int b1 = hi - base < 16 ? (int)(hi - base) : 16;
+#pragma unroll
+        for (int b = 0; b < 16; ++b)
+            if (b >= b0 && b < b1) step_rt(S, W, (wv[b >> 2] >> (8 * (b & 3))) & 255u, M, F);
+        uint32_t any = 0, acc = 0;
+#pragma unroll
+        for (int w = 0; w < kWMax; ++w) {
+            any |= S[w];
+            acc |= (w == aw) ? S[w] : 0u;
+        }
+        if (any == 0) return 0;
+        if (suffix_any && (acc & abit)) return 1;
+    }
+    uint32_t acc = 0;
+#pragma unroll
+    for (int w = 0; w < kWMax; ++w) acc |= (w == aw) ? S[w] : 0u;
+    return (acc & abit) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_items(ItemKArgs a) {
+    extern __shared__ uint32_t lds[];
+    __shared__ int s_item;
+    int loaded = -1;
+    const int total = *a.n_items;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.head, 1);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= total) break;  // every wave of the workgroup sees the same value and exits
+        const WorkItem item = a.items[it];
+        const ProgDesc& P = a.progs[item.prog];
+        if (item.prog != loaded) {
+            for (int i = threadIdx.x; i < 256 * P.W; i += blockDim.x) lds[i] = P.bytemask[i];
+            for (int i = threadIdx.x; i < P.L * P.W; i += blockDim.x) lds[256 * P.W + i] = P.follow[i];
+            loaded = item.prog;
+            __syncthreads();
+        }
+        for (int k = threadIdx.x; k < item.count; k += blockDim.x) {
+            const int64_t line = a.ids ? (int64_t)a.ids[item.line0 + k] : item.line0 + k;
+            const int64_t lo = a.offsets[line], hi = a.offsets[line + 1];
+            const int r = match_one(P.first, lds, lds + 256 * P.W, P.L, P.W, P.suffix_any, a.bytes, lo, hi);
+            a.out[item.out0 + line] = (uint8_t)r;
+        }
+        __syncthreads();  // the tables and s_item are reused by the next item
+    }
+}
+
+// -- bucketing -------------------------------------------------------------
+__device__ __forceinline__ int bucket_of(int64_t len, const int32_t* edges, int n_edges) {
+    int b = 0;
+    while (b < n_edges && len > edges[b]) ++b;
+    return b;  // bucket b holds lengths in (edges[b-1], edges[b]]; the last one everything longer
+}
+
+struct BucketArgs {
+    int32_t edges[kMaxBuckets];
+    int32_t n_edges;
+    const int64_t* offsets;
+    int64_t n;
+    int32_t* counts;   // [n_buckets]
+    int32_t* cursor;   // [n_buckets]
+    int32_t* start;    // [n_buckets + 1]
+    int32_t* item_start;  // [n_buckets]
+    int32_t* ids;      // [n]
+    WorkItem* items;
+    int32_t* n_items;
+    int32_t* head;
+    int32_t n_progs;
+    int32_t block_lines;
+    int64_t out_stride;
+};
+
+__global__ void k_bucket_clear(BucketArgs a) {
+    const int nb = a.n_edges + 1;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        a.counts[i] = 0;
+        a.cursor[i] = 0;
+    }
+    if (threadIdx.x == 0) {
+        *a.n_items = 0;
+        *a.head = 0;
+    }
+}
+
+__global__ void k_bucket_count(BucketArgs a) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = bucket_of(a.offsets[i + 1] - a.offsets[i], a.edges, a.n_edges);
+        atomicAdd(&a.counts[b], 1);
+    }
+}
+
+// one thread: bucket starts, and where each bucket's items begin in the
+// queue (longest bucket first; within a bucket, program-major so that a
+// workgroup's successive items tend to share the staged tables)
+__global__ void k_bucket_scan(BucketArgs a) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int nb = a.n_edges + 1;
+    int32_t s = 0;
+    for (int b = 0; b < nb; ++b) {
+        a.start[b] = s;
+        s += a.counts[b];
+    }
+    a.start[nb] = s;
+    int32_t k = 0;
+    for (int b = nb - 1; b >= 0; --b) {
+        a.item_start[b] = k;
+        k += (a.counts[b] + a.block_lines - 1) / a.block_lines * a.n_progs;
+    }
+    *a.n_items = k;
+}
+
+__global__ void k_bucket_fill(BucketArgs a) {
+    const int nb = a.n_edges + 1;
+    const int32_t total = *a.n_items;
+    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < total; k += gridDim.x * blockDim.x) {
+        int b = -1;
+        for (int c = 0; c < nb; ++c) {
+            const int32_t tiles = (a.counts[c] + a.block_lines - 1) / a.block_lines;
+            if (tiles > 0 && k >= a.item_start[c] && k < a.item_start[c] + tiles * a.n_progs) b = c;
+        }
+        if (b < 0) continue;  // not reached: every k < total lies in one bucket's range
+        const int32_t tiles = (a.counts[b] + a.block_lines - 1) / a.block_lines;
+        const int32_t local = k - a.item_start[b];
+        const int32_t p = local / tiles, t = local % tiles;
+        WorkItem w;
+        w.prog = p;
+        w.count = a.counts[b] - t * a.block_lines < a.block_lines ? a.counts[b] - t * a.block_lines : a.block_lines;
+        w.line0 = a.start[b] + (int64_t)t * a.block_lines;
+        w.out0 = (int64_t)p * a.out_stride;
+        a.items[k] = w;
+    }
+}
+
+__global__ void k_bucket_scatter(BucketArgs a) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = bucket_of(a.offsets[i + 1] - a.offsets[i], a.edges, a.n_edges);
+        const int32_t pos = atomicAdd(&a.cursor[b], 1);
+        a.ids[a.start[b] + pos] = (int32_t)i;
+    }
+}
+
+}  // namespace
+
+int64_t multi_workspace_bytes(int64_t n, int32_t n_progs, int32_t n_buckets, int32_t block_lines) {
+    auto al = [](int64_t x) { return (x + 255) & ~int64_t(255); };
+    if (block_lines <= 0) block_lines = 256;
+    const int64_t max_items = (n / block_lines + n_buckets + 1) * (int64_t)n_progs;
+    return al(4 * (int64_t)(4 * (n_buckets + 1) + 4)) + al(4 * n) + al((int64_t)sizeof(WorkItem) * max_items);
+}
+
+int launch_multi(const MultiArgs& m) {
+    const hipStream_t st = (hipStream_t)m.stream;
+    const int nb = m.n_edges + 1;
+    uint8_t* w = static_cast<uint8_t*>(m.work);
+    auto al = [](int64_t x) { return (x + 255) & ~int64_t(255); };
+    BucketArgs b;
+    for (int i = 0; i < kMaxBuckets; ++i) b.edges[i] = i < m.n_edges ? m.edges[i] : 0;
+    b.n_edges = m.n_edges;
+    b.offsets = m.offsets;
+    b.n = m.n;
+    int32_t* small = reinterpret_cast<int32_t*>(w);
+    b.counts = small;
+    b.cursor = small + (nb + 1);
+    b.start = small + 2 * (nb + 1);
+    b.item_start = small + 3 * (nb + 1);
+    b.n_items = small + 4 * (nb + 1);
+    b.head = small + 4 * (nb + 1) + 1;
+    const int64_t o_ids = al(4 * (int64_t)(4 * (nb + 1) + 4));
+    b.ids = reinterpret_cast<int32_t*>(w + o_ids);
+    b.items = reinterpret_cast<WorkItem*>(w + o_ids + al(4 * m.n));
+    b.n_progs = m.n_progs;
+    b.block_lines = m.block_lines;
+    b.out_stride = m.n;
+    const int gs = (int)((m.n + 255) / 256 < 4096 ? (m.n + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_bucket_clear, dim3(1), dim3(64), 0, st, b);
+    if (m.n > 0) hipLaunchKernelGGL(k_bucket_count, dim3(gs > 0 ? gs : 1), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(64), 0, st, b);
+    if (m.n > 0) hipLaunchKernelGGL(k_bucket_scatter, dim3(gs > 0 ? gs : 1), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_bucket_fill, dim3(1024), dim3(256), 0, st, b);
+    if (hipError_t e = hipGetLastError()) return (int)e;
+    ItemKArgs k;
+    for (int i = 0; i < m.n_progs; ++i) k.progs[i] = m.progs[i];
+    k.n_progs = m.n_progs;
+    k.block_lines = m.block_lines;
+    k.bytes = m.bytes;
+    k.offsets = m.offsets;
+    k.ids = b.ids;
+    k.items = b.items;
+    k.n_items = b.n_items;
+    k.head = b.head;
+    k.out = m.out;
+    int max_lds_words = 0;
+    for (int i = 0; i < m.n_progs; ++i) {
+        const int words = (256 + m.progs[i].L) * m.progs[i].W;
+        if (words > max_lds_words) max_lds_words = words;
+    }
+    const int grid = m.grid > 0 ? m.grid : 1024;
+    hipLaunchKernelGGL(k_items, dim3(grid), dim3(m.block_lines), 4 * (size_t)max_lds_words, st, k);
+    return (int)hipGetLastError();
+}
+
+int launch_items(const ItemsArgs& m) {
+    ItemKArgs k;
+    for (int i = 0; i < m.n_progs; ++i) k.progs[i] = m.progs[i];
+    k.n_progs = m.n_progs;
+    k.block_lines = m.block;
+    k.bytes = m.bytes;
+    k.offsets = m.offsets;
+    k.ids = nullptr;
+    k.items = m.items;
+    k.n_items = m.n_items;
+    k.head = m.head;
+    k.out = m.out;
+    int max_lds_words = 0;
+    for (int i = 0; i < m.n_progs; ++i) {
+        const int words = (256 + m.progs[i].L) * m.progs[i].W;
+        if (words > max_lds_words) max_lds_words = words;
+    }
+    hipLaunchKernelGGL(k_items, dim3(m.grid > 0 ? m.grid : 1024), dim3(m.block > 0 ? m.block : 256),
+                       4 * (size_t)max_lds_words, (hipStream_t)m.stream, k);
+    return (int)hipGetLastError();
+}
+
+}  // namespace rx

@@ -46,6 +46,21 @@ class rx_node(ctypes.Structure):
                 ("label", ctypes.c_int32), ("cont", ctypes.c_int32)]
 
 
+class rx_multi_config(ctypes.Structure):
+    _fields_ = [("n_edges", ctypes.c_int32), ("edges", ctypes.c_int32 * 15), ("block", ctypes.c_int32),
+                ("grid", ctypes.c_int32)]
+
+
+def multi_config(edges=None, block=0, grid=0) -> "rx_multi_config":
+    c = rx_multi_config()
+    if edges:
+        c.n_edges = len(edges)
+        for i, e in enumerate(edges):
+            c.edges[i] = int(e)
+    c.block, c.grid = int(block), int(grid)
+    return c
+
+
 class rx_launch(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("block", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("unroll", ctypes.c_int32)]
@@ -68,6 +83,9 @@ SIGNATURES = {
     "rx_program_jit": (ctypes.c_int, [_VP, ctypes.c_char_p]),
     "rx_program_jit_source": (ctypes.c_int, [_VP, ctypes.c_char_p, _SZ, ctypes.POINTER(_SZ)]),
     "rx_program_jit_stats": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "rx_match_multi_workspace": (ctypes.c_int64, [_I64, _I32, ctypes.POINTER(rx_multi_config)]),
+    "rx_match_multi": (ctypes.c_int, [ctypes.POINTER(_VP), _I32, _VP, _VP, _I64, _VP, _VP, _SZ,
+                                      ctypes.POINTER(rx_multi_config), _VP]),
     "rx_last_error": (ctypes.c_char_p, []),
     "rx_version": (ctypes.c_char_p, []),
 }
@@ -256,6 +274,32 @@ def match_fixed(prog: Program, data, length: int, n: int = None, out=None, launc
         L = launch if isinstance(launch, rx_launch) else rx_launch(*launch)
         _check(lib().rx_match_fixed_ex(prog.handle, ctypes.c_void_p(data.data_ptr()), int(length), int(n),
                                        ctypes.c_void_p(out.data_ptr()), ctypes.byref(L), sh))
+    return out
+
+
+def match_multi(progs, data, offsets, out=None, config=None, work=None, stream=None):
+    """Every string against every program in one batched launch: returns a (P, n) uint8 tensor."""
+    import torch
+
+    n = offsets.numel() - 1
+    P = len(progs)
+    for p in progs:
+        if p._dev_buf is None:
+            p.upload(device=offsets.device, stream=stream)
+    cfg = config if config is not None else rx_multi_config()
+    need = lib().rx_match_multi_workspace(n, P, ctypes.byref(cfg))
+    if need < 0:
+        _check(int(need))
+    if work is None or work.numel() < need + 256:
+        work = torch.empty(int(need) + 256, dtype=torch.uint8, device=offsets.device)
+    wptr = work.data_ptr() + ((-work.data_ptr()) % 256)
+    if out is None:
+        out = torch.empty((P, max(n, 0)), dtype=torch.uint8, device=offsets.device)
+    handles = (ctypes.c_void_p * P)(*[p.handle.value for p in progs])
+    dptr = data.data_ptr() if data.numel() else offsets.data_ptr()
+    _check(lib().rx_match_multi(handles, P, ctypes.c_void_p(dptr), ctypes.c_void_p(offsets.data_ptr()), n,
+                                ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(wptr), int(need),
+                                ctypes.byref(cfg), _stream_handle(stream)))
     return out
 
 

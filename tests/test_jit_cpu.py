@@ -14,6 +14,17 @@ import oracle
 from paper_1108_3126_amd import rx
 from paper_1108_3126_amd import workloads as W
 
+# v_perm_b32 on the host: byte i of the result is byte sel[i] of the 64-bit value {hi, lo}
+PERM_CPU = r"""
+static inline unsigned rx_perm_cpu(unsigned hi, unsigned lo, unsigned sel) {
+    const unsigned long long v = ((unsigned long long)hi << 32) | lo;
+    unsigned r = 0;
+    for (int i = 0; i < 4; ++i) r |= (unsigned)((v >> (8 * ((sel >> (8 * i)) & 7))) & 0xff) << (8 * i);
+    return r;
+}
+#define RX_PERM(hi, lo, sel) rx_perm_cpu((hi), (lo), (sel))
+"""
+
 DRIVER = r"""
 extern "C" int rx_cpu_run(const unsigned char* bytes, long long length, long long n, unsigned char* out) {
     for (long long g = 0; g < n; g += 32) {
@@ -44,7 +55,7 @@ extern "C" int rx_cpu_run(const unsigned char* bytes, long long length, long lon
 def cpu_circuit(p: rx.Program):
     src = p.jit_source()
     host_part = src.split("// ---- device kernel ----")[0]
-    code = "#define __device__\n#define __forceinline__ inline\n" + host_part + DRIVER
+    code = "#define __device__\n#define __forceinline__ inline\n" + PERM_CPU + host_part + DRIVER
     d = tempfile.mkdtemp(prefix="rxjit")
     cpp, so = os.path.join(d, "c.cpp"), os.path.join(d, "c.so")
     open(cpp, "w").write(code)
