@@ -264,8 +264,109 @@ int rx_match_multi(const rx_program* const* progs, int32_t n_progs, const uint8_
                    const int64_t* d_offsets, int64_t n, uint8_t* d_out, void* d_work, size_t work_bytes,
                    const rx_multi_config* cfg, void* stream);
 
+/*
+ * Autotuner for rx_match / rx_match_fixed: successive halving over the kernel
+ * variants (bit-sliced circuit when compiled, one lane per string, one
+ * wavefront per string) and their workgroup and grid sizes, timed with HIP
+ * events on `stream`.  d_offsets NULL means fixed-length strings of `length`
+ * bytes (rx_match_fixed), otherwise offsets (rx_match; length ignored).
+ * d_out receives the results (n bytes).  Every candidate must return the same
+ * bits as the first (the parallel schedule does not change the result,
+ * Thm. 7.2); a disagreement fails with RX_EINVAL.  budget_runs bounds the
+ * timed launches.  Synchronises `stream`.  *best is the fastest launch shape,
+ * *best_ms its mean device time, *n_candidates the candidates tried.
+ */
+int rx_autotune(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t length, int64_t n,
+                uint8_t* d_out, int32_t budget_runs, rx_launch* best, double* best_ms, int32_t* n_candidates,
+                void* stream);
+
+/* Autotuner for rx_match_multi: bucket ladders (powers of two, a finer
+ * geometric ladder, a coarse one) x workgroup size x grid, same rules as
+ * rx_autotune.  d_work must hold rx_match_multi_workspace(n, n_progs, cfg)
+ * bytes for cfg = {15 edges, block 64} (the largest candidate). */
+int rx_autotune_multi(const rx_program* const* progs, int32_t n_progs, const uint8_t* d_bytes,
+                      const int64_t* d_offsets, int64_t n, uint8_t* d_out, void* d_work, size_t work_bytes,
+                      int32_t budget_runs, rx_multi_config* best, double* best_ms, int32_t* n_candidates,
+                      void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of match requests.
+ *
+ * A server owns a fixed device footprint, allocated once by rx_server_create:
+ * `slots` step buffers (strings, offsets, work items, results) plus an arena of
+ * `program_slots` resident program tables (64 KiB each).  That footprint must
+ * fit `hbm_budget`.  Clients submit requests from any thread; a scheduler
+ * thread admits pending requests into the next free step while they fit its
+ * capacity, so requests that arrive while steps run join the next step and
+ * steps on different slots overlap on the device.  Each step is one launch of
+ * the batched item kernel framed by host<->device copies, replayed as a
+ * hipGraph when use_graph is set.  Programs are cached by their AST bytes,
+ * classes and flags.  A request's bits do not depend on what it was batched
+ * with.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int64_t hbm_budget;     /* device bytes the server may hold (default 2 GiB) */
+    int64_t step_bytes;     /* string bytes per step (default 64 MiB); larger requests are refused */
+    int64_t step_strings;   /* strings per step (default 262144); larger requests are refused */
+    int32_t step_requests;  /* requests per step (default 512) */
+    int32_t slots;          /* steps in flight (default 2, at most 8) */
+    int32_t use_graph;      /* 1: replay each slot's step as a hipGraph with updated node parameters */
+    int32_t block;          /* strings per work item: 64, 128 or 256 (default 256) */
+    int32_t grid;           /* persistent workgroups per step (default 4 per compute unit) */
+    int32_t program_slots;  /* resident programs (default 1024) */
+} rx_server_config;
+
+typedef struct {
+    int64_t submitted, completed, rejected, queued, max_queue;
+    int64_t steps, graph_steps, strings, bytes;
+    int64_t cache_hits, cache_misses, cache_evictions;
+    double p50_us, p99_us, mean_us, max_us; /* latency: submit -> results on the host */
+    double wall_s;                          /* first submit -> last completion */
+} rx_server_counters;
+
+typedef struct rx_server rx_server;
+
+/* Creates a server and its scheduler thread on the current device.  cfg may
+ * be NULL (defaults).  Errors: RX_EINVAL, RX_ETOOBIG (footprint above the
+ * budget), RX_EHIP. */
+int rx_server_create(const rx_server_config* cfg, rx_server** out);
+
+/* Drains pending requests, stops the scheduler and frees everything. */
+void rx_server_destroy(rx_server* srv);
+
+/* Submits one request: the expression (as for rx_compile) and n host strings
+ * (host_bytes[host_offsets[i] .. host_offsets[i+1])), copied before the call
+ * returns.  *req_id identifies it for rx_server_wait.  Never blocks on the
+ * device.  Errors: RX_EINVAL (malformed AST or batch), RX_ETOOBIG (above one
+ * step's capacity or more than 511 leaves), RX_EHIP (the server failed). */
+int rx_server_submit(rx_server* srv, const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx_class* classes,
+                     int32_t n_classes, uint32_t flags, const uint8_t* host_bytes, const int64_t* host_offsets,
+                     int64_t n, int64_t* req_id);
+
+/* Waits for a request (timeout_us < 0: forever), copies its n result bytes
+ * into host_out (may be NULL) and forgets it.  Errors: RX_EINVAL (unknown id),
+ * RX_ETIMEOUT (still running; the request stays waitable), RX_EHIP. */
+int rx_server_wait(rx_server* srv, int64_t req_id, uint8_t* host_out, int64_t timeout_us);
+
+/* Counters and latency percentiles since creation or the last reset. */
+int rx_server_stats(rx_server* srv, rx_server_counters* out);
+int rx_server_reset_stats(rx_server* srv);
+
+/* The plain per-request path the server is measured against: compile, upload,
+ * copy the strings in, one rx_match launch, copy the bits out, synchronise,
+ * free -- all inside the call.  Same arguments as rx_server_submit. */
+int rx_plain_match(const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx_class* classes, int32_t n_classes,
+                   uint32_t flags, const uint8_t* host_bytes, const int64_t* host_offsets, int64_t n,
+                   uint8_t* host_out);
+
 /* Thread-local message of the last failed call on this host thread. */
 const char* rx_last_error(void);
+
+/* Measurement only: a plain coalesced device-to-device copy of `bytes`
+ * (a multiple of 16; both buffers 16-byte aligned) on `stream`.  It gives the
+ * practical streaming ceiling of the memory system and calibrates hardware
+ * byte counters against a kernel whose traffic is known exactly. */
+int rx_stream_copy(void* d_dst, const void* d_src, int64_t bytes, void* stream);
 
 /* Library version string. */
 const char* rx_version(void);

@@ -335,6 +335,39 @@ int rx_match_multi(const rx_program* const* progs, int32_t n_progs, const uint8_
     RX_GUARD_END
 }
 
+int rx_autotune(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t length, int64_t n,
+                uint8_t* d_out, int32_t budget_runs, rx_launch* best, double* best_ms, int32_t* n_candidates,
+                void* stream) {
+    RX_GUARD_BEGIN
+    if (!prog || !best) return fail(RX_EINVAL, "NULL argument");
+    if (n <= 0) return fail(RX_EINVAL, "autotune needs at least one string");
+    const Program* P = reinterpret_cast<const Program*>(prog);
+    if (!P->dev) return fail(RX_ENOTUPLOADED, "program has not been uploaded");
+    int nc = 0;
+    int rc = autotune_single(P, d_bytes, d_offsets, length, n, d_out, budget_runs > 0 ? budget_runs : 64, best, best_ms,
+                             &nc, stream);
+    if (n_candidates) *n_candidates = nc;
+    if (rc == RX_OK) clear_error();
+    return rc;
+    RX_GUARD_END
+}
+
+int rx_autotune_multi(const rx_program* const* progs, int32_t n_progs, const uint8_t* d_bytes,
+                      const int64_t* d_offsets, int64_t n, uint8_t* d_out, void* d_work, size_t work_bytes,
+                      int32_t budget_runs, rx_multi_config* best, double* best_ms, int32_t* n_candidates,
+                      void* stream) {
+    RX_GUARD_BEGIN
+    if (!progs || !best) return fail(RX_EINVAL, "NULL argument");
+    if (n <= 0) return fail(RX_EINVAL, "autotune needs at least one string");
+    int nc = 0;
+    int rc = autotune_multi(progs, n_progs, d_bytes, d_offsets, n, d_out, d_work, work_bytes,
+                            budget_runs > 0 ? budget_runs : 96, best, best_ms, &nc, stream);
+    if (n_candidates) *n_candidates = nc;
+    if (rc == RX_OK) clear_error();
+    return rc;
+    RX_GUARD_END
+}
+
 int rx_program_jit(rx_program* prog, const char* arch) {
     RX_GUARD_BEGIN
     if (!prog) return fail(RX_EINVAL, "program is NULL");
@@ -369,6 +402,16 @@ int rx_program_jit_stats(const rx_program* prog, int32_t* ready, int32_t* state_
 }
 
 const char* rx_last_error(void) { return last_error_cstr(); }
+
+int rx_stream_copy(void* d_dst, const void* d_src, int64_t bytes, void* stream) {
+    if (bytes < 0 || (bytes % 16) != 0) return fail(RX_EINVAL, "bytes must be a non-negative multiple of 16");
+    if (bytes && (!d_dst || !d_src)) return fail(RX_EINVAL, "NULL device buffer");
+    if ((reinterpret_cast<uintptr_t>(d_dst) | reinterpret_cast<uintptr_t>(d_src)) & 15)
+        return fail(RX_EINVAL, "buffers must be 16-byte aligned");
+    if (!bytes) return RX_OK;
+    if (int e = launch_stream_copy(d_dst, d_src, bytes, stream)) return hip_fail(e, "copy launch");
+    return RX_OK;
+}
 
 const char* rx_version(void) { return "rx-mi355x 0.1 (gfx950)"; }
 

@@ -93,9 +93,31 @@ struct ItemsArgs {
     void* stream;
 };
 
+struct Copy {
+    void* dst;
+    const void* src;
+    size_t bytes;
+};
+struct StepDesc {          // one serving step
+    Copy h2d[3];           // strings, offsets, work items (with the queue header)
+    ItemsArgs items;       // item kernel arguments
+    Copy d2h;              // results
+};
+struct StepGraph;
+int step_launch_direct(const StepDesc& d, void* stream);
+int step_graph_launch(StepGraph** g, const StepDesc& d, void* stream);
+void step_graph_destroy(StepGraph* g);
+
 int64_t multi_workspace_bytes(int64_t n, int32_t n_progs, int32_t n_buckets, int32_t block_lines);
 int launch_multi(const MultiArgs& m);
 int launch_items(const ItemsArgs& m);
+
+// autotuner (rx_autotune.cpp)
+int autotune_single(const Program* P, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t length, int64_t n,
+                    uint8_t* d_out, int budget_runs, rx_launch* best, double* best_ms, int* n_cands, void* stream);
+int autotune_multi(const rx_program* const* progs, int32_t n_progs, const uint8_t* d_bytes, const int64_t* d_offsets,
+                   int64_t n, uint8_t* d_out, void* d_work, size_t work_bytes, int budget_runs, rx_multi_config* best,
+                   double* best_ms, int* n_cands, void* stream);
 
 // error reporting (thread-local message)
 int fail(int code, const std::string& msg);
@@ -132,6 +154,7 @@ int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, 
                         void* stream);
 int launch_wave(const LaunchArgs& a);
 const char* hip_error_string(int err);
+int launch_stream_copy(void* dst, const void* src, int64_t bytes, void* stream);
 int hip_current_device(int* dev);
 int hip_memcpy_h2d_async(void* dst, const void* src, size_t n, void* stream);
 int hip_cu_count(int* cus);

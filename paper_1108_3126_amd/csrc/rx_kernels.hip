@@ -245,6 +245,25 @@ int launch_wave(const LaunchArgs& a) {
     return (int)hipGetLastError();
 }
 
+// Streaming copy (measurement only): the practical HBM ceiling and the
+// calibration of byte counters against a kernel of known traffic.
+__global__ __launch_bounds__(256) void k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+int launch_stream_copy(void* dst, const void* src, int64_t bytes, void* stream) {
+    const int64_t n16 = bytes / 16;
+    int cus = 256;
+    hip_cu_count(&cus);
+    int64_t grid = (n16 + 255) / 256;
+    if (grid > (int64_t)cus * 16) grid = (int64_t)cus * 16;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
+                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+    return (int)hipGetLastError();
+}
+
 const char* hip_error_string(int err) { return hipGetErrorString((hipError_t)err); }
 
 int hip_current_device(int* dev) { return (int)hipGetDevice(dev); }

@@ -291,4 +291,114 @@ int launch_items(const ItemsArgs& m) {
     return (int)hipGetLastError();
 }
 
+// -- one serving step: copies in, the item kernel, results out ----------------
+namespace {
+
+ItemKArgs item_kargs(const ItemsArgs& m) {
+    ItemKArgs k;
+    for (int i = 0; i < kMaxItemProgs; ++i) k.progs[i] = i < m.n_progs ? m.progs[i] : ProgDesc{};
+    k.n_progs = m.n_progs;
+    k.block_lines = m.block;
+    k.bytes = m.bytes;
+    k.offsets = m.offsets;
+    k.ids = nullptr;
+    k.items = m.items;
+    k.n_items = m.n_items;
+    k.head = m.head;
+    k.out = m.out;
+    return k;
+}
+
+constexpr unsigned kStepLds = 4u * (256u + 511u) * (unsigned)kLaneMaxWords;  // the largest program a step may hold
+
+}  // namespace
+
+int step_launch_direct(const StepDesc& d, void* stream) {
+    const hipStream_t st = (hipStream_t)stream;
+    for (int i = 0; i < 3; ++i)
+        if (d.h2d[i].bytes)
+            if (hipError_t e = hipMemcpyAsync(d.h2d[i].dst, d.h2d[i].src, d.h2d[i].bytes, hipMemcpyHostToDevice, st))
+                return (int)e;
+    ItemKArgs k = item_kargs(d.items);
+    hipLaunchKernelGGL(k_items, dim3(d.items.grid), dim3(d.items.block), kStepLds, st, k);
+    if (hipError_t e = hipGetLastError()) return (int)e;
+    if (d.d2h.bytes)
+        if (hipError_t e = hipMemcpyAsync(d.d2h.dst, d.d2h.src, d.d2h.bytes, hipMemcpyDeviceToHost, st)) return (int)e;
+    return 0;
+}
+
+struct StepGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t copy[3] = {}, kernel = nullptr, back = nullptr;
+    ItemKArgs args;
+};
+
+int step_graph_launch(StepGraph** pg, const StepDesc& d, void* stream) {
+    const hipStream_t st = (hipStream_t)stream;
+    auto sz = [](size_t b) { return b ? b : (size_t)1; };
+    StepGraph* g = *pg;
+    if (!g) {
+        g = new StepGraph;
+        hipError_t e = hipGraphCreate(&g->graph, 0);
+        hipGraphNode_t prev = nullptr;
+        for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+            e = hipGraphAddMemcpyNode1D(&g->copy[i], g->graph, prev ? &prev : nullptr, prev ? 1 : 0, d.h2d[i].dst,
+                                        d.h2d[i].src, sz(d.h2d[i].bytes), hipMemcpyHostToDevice);
+            prev = g->copy[i];
+        }
+        g->args = item_kargs(d.items);
+        if (e == hipSuccess) {
+            hipKernelNodeParams kp = {};
+            void* params[] = {&g->args};
+            kp.func = (void*)k_items;
+            kp.gridDim = dim3(d.items.grid);
+            kp.blockDim = dim3(d.items.block);
+            kp.sharedMemBytes = kStepLds;
+            kp.kernelParams = params;
+            kp.extra = nullptr;
+            e = hipGraphAddKernelNode(&g->kernel, g->graph, &prev, 1, &kp);
+            prev = g->kernel;
+        }
+        if (e == hipSuccess)
+            e = hipGraphAddMemcpyNode1D(&g->back, g->graph, &prev, 1, d.d2h.dst, d.d2h.src, sz(d.d2h.bytes),
+                                        hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            step_graph_destroy(g);
+            return (int)e;
+        }
+        *pg = g;
+        return (int)hipGraphLaunch(g->exec, st);
+    }
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 3 && e == hipSuccess; ++i)
+        e = hipGraphExecMemcpyNodeSetParams1D(g->exec, g->copy[i], d.h2d[i].dst, d.h2d[i].src, sz(d.h2d[i].bytes),
+                                              hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        g->args = item_kargs(d.items);
+        hipKernelNodeParams kp = {};
+        void* params[] = {&g->args};
+        kp.func = (void*)k_items;
+        kp.gridDim = dim3(d.items.grid);
+        kp.blockDim = dim3(d.items.block);
+        kp.sharedMemBytes = kStepLds;
+        kp.kernelParams = params;
+        kp.extra = nullptr;
+        e = hipGraphExecKernelNodeSetParams(g->exec, g->kernel, &kp);
+    }
+    if (e == hipSuccess)
+        e = hipGraphExecMemcpyNodeSetParams1D(g->exec, g->back, d.d2h.dst, d.d2h.src, sz(d.d2h.bytes),
+                                              hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipGraphLaunch(g->exec, st);
+    return (int)e;
+}
+
+void step_graph_destroy(StepGraph* g) {
+    if (!g) return;
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    delete g;
+}
+
 }  // namespace rx

@@ -61,6 +61,19 @@ def multi_config(edges=None, block=0, grid=0) -> "rx_multi_config":
     return c
 
 
+class rx_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("step_bytes", ctypes.c_int64), ("step_strings", ctypes.c_int64),
+                ("step_requests", ctypes.c_int32), ("slots", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("grid", ctypes.c_int32), ("program_slots", ctypes.c_int32)]
+
+
+class rx_server_counters(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "rejected", "queued", "max_queue", "steps",
+                                               "graph_steps", "strings", "bytes", "cache_hits", "cache_misses",
+                                               "cache_evictions")] + \
+               [(k, ctypes.c_double) for k in ("p50_us", "p99_us", "mean_us", "max_us", "wall_s")]
+
+
 class rx_launch(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("block", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("unroll", ctypes.c_int32)]
@@ -86,6 +99,20 @@ SIGNATURES = {
     "rx_match_multi_workspace": (ctypes.c_int64, [_I64, _I32, ctypes.POINTER(rx_multi_config)]),
     "rx_match_multi": (ctypes.c_int, [ctypes.POINTER(_VP), _I32, _VP, _VP, _I64, _VP, _VP, _SZ,
                                       ctypes.POINTER(rx_multi_config), _VP]),
+    "rx_autotune": (ctypes.c_int, [_VP, _VP, _VP, _I64, _I64, _VP, _I32, ctypes.POINTER(rx_launch),
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I32), _VP]),
+    "rx_autotune_multi": (ctypes.c_int, [ctypes.POINTER(_VP), _I32, _VP, _VP, _I64, _VP, _VP, _SZ, _I32,
+                                         ctypes.POINTER(rx_multi_config), ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(_I32), _VP]),
+    "rx_server_create": (ctypes.c_int, [ctypes.POINTER(rx_server_config), ctypes.POINTER(_VP)]),
+    "rx_server_destroy": (None, [_VP]),
+    "rx_server_submit": (ctypes.c_int, [_VP, _VP, _I32, _I32, _VP, _I32, _U32, _VP, _VP, _I64,
+                                        ctypes.POINTER(_I64)]),
+    "rx_server_wait": (ctypes.c_int, [_VP, _I64, _VP, _I64]),
+    "rx_server_stats": (ctypes.c_int, [_VP, ctypes.POINTER(rx_server_counters)]),
+    "rx_server_reset_stats": (ctypes.c_int, [_VP]),
+    "rx_plain_match": (ctypes.c_int, [_VP, _I32, _I32, _VP, _I32, _U32, _VP, _VP, _I64, _VP]),
+    "rx_stream_copy": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
     "rx_last_error": (ctypes.c_char_p, []),
     "rx_version": (ctypes.c_char_p, []),
 }
@@ -301,6 +328,13 @@ def match_multi(progs, data, offsets, out=None, config=None, work=None, stream=N
                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(wptr), int(need),
                                 ctypes.byref(cfg), _stream_handle(stream)))
     return out
+
+
+def stream_copy(dst, src, nbytes=None, stream=None):
+    """Measurement-only coalesced copy between two device tensors."""
+    nbytes = int(nbytes if nbytes is not None else src.numel() * src.element_size())
+    _check(lib().rx_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                                _stream_handle(stream)))
 
 
 def version() -> str:
