@@ -50,6 +50,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1000000, help="strings the CPU oracle times")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--check", type=int, default=2000, help="sampled strings checked against the oracle")
+    ap.add_argument("--serving", type=int, default=1000, help="requests in the serving comparison (0 = skip)")
+    ap.add_argument("--copy-only", action="store_true", help="only run the stream-copy probe (counter calibration)")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 28)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -64,6 +67,9 @@ def main():
     from paper_1108_3126_amd import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.copy_only:
+        print(json.dumps(copy_probe(torch, rx, dev, args.copy_bytes, reps=max(args.steps, 1))), flush=True)
+        return
     t0 = time.time()
     prog = W.single_program(1)
     strings, planted = W.single_strings(prog, seed=1, n=args.strings, length=args.length)
@@ -140,6 +146,12 @@ def main():
                "sample": f"first {n_cpu} of the {strings.n} strings ({cpu_bytes} bytes), {cdt:.1f} s"}
         log(f"cpu oracle: {cpu}")
 
+    copy = copy_probe(torch, rx, dev, 1 << 28, reps=10)
+    log(f"copy probe: {copy}")
+    serving = run_serving(args, torch) if args.serving > 0 else None
+    if serving:
+        log(f"serving: {serving}")
+
     variant_name = {0: "auto", 1: "lane", 2: "wave", 3: "sliced"}[args.variant]
     if args.variant == 0:
         variant_name = "sliced" if (args.layout == "fixed" and not args.no_jit) else "lane"
@@ -177,8 +189,138 @@ def main():
             "traffic": None,
         },
         "cpu_baseline": cpu,
+        "copy_probe": copy,
+        "serving": serving,
     }
     print(json.dumps(rec), flush=True)
+
+
+def copy_probe(torch, rx, dev, nbytes, reps=10):
+    """Practical streaming ceiling: a coalesced device copy (read + write bytes per second)."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = [torch.empty(nbytes, dtype=torch.uint8, device=dev) for _ in range(2)]
+    a.fill_(1)
+    rx.stream_copy(b[0], a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(reps):
+        rx.stream_copy(b[i & 1], a if i % 2 == 0 else b[0])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"bytes": nbytes, "ms": round(ms, 4), "read_write_GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
+def run_serving(args, torch):
+    """Batched server against the per-request plain path on the same requests and Poisson rate."""
+    import threading
+    import queue
+
+    import oracle
+    from paper_1108_3126_amd import server
+    from paper_1108_3126_amd import workloads as W
+
+    R = args.serving
+    t0 = time.time()
+    reqs = [W.serving_request(3, i) for i in range(R)]
+    total_bytes = sum(int(s.offsets[-1]) for _, s in reqs)
+    log(f"serving: {R} requests, {total_bytes / 1e6:.1f} MB, generated in {time.time() - t0:.1f}s")
+    # warm up both paths (first-touch costs) on a few requests
+    for p, s in reqs[:3]:
+        server.plain_match(p, s.data, s.offsets)
+    # capacity of the plain path: serial, back to back
+    c0 = time.perf_counter()
+    plain_out = [server.plain_match(p, s.data, s.offsets) for p, s in reqs]
+    plain_cap = R / (time.perf_counter() - c0)
+    srv = server.Server(use_graph=True)
+    for p, s in reqs[:3]:
+        srv.wait(srv.submit(p, s.data, s.offsets))
+    srv.reset_stats()
+    c0 = time.perf_counter()
+    ids = [srv.submit(p, s.data, s.offsets) for p, s in reqs]
+    srv_out = [srv.wait(r) for r in ids]
+    srv_cap = R / (time.perf_counter() - c0)
+    st_cap = srv.stats()
+    exact = all(np.array_equal(a, b) for a, b in zip(plain_out, srv_out))
+    # oracle on a sample of every 25th request, 20 strings each
+    for k in range(0, R, 25):
+        p, s = reqs[k]
+        if s.n == 0:
+            continue
+        idx = np.unique(np.linspace(0, s.n - 1, min(20, s.n)).astype(np.int64))
+        want = oracle.match(p.ast, p.root, p.classes, p.search, s.data, s.offsets, index=idx)
+        exact = exact and bool(np.array_equal(srv_out[k][idx], want))
+
+    rate = 0.9 * plain_cap
+    arrivals = W.poisson_arrivals(3, R, rate)
+
+    def run_plain_at_rate():
+        q, lat = queue.Queue(), []
+
+        def worker():
+            while True:
+                item = q.get()
+                if item is None:
+                    return
+                t_arr, (p, s) = item
+                server.plain_match(p, s.data, s.offsets)
+                lat.append(time.perf_counter() - t_arr)
+
+        th = threading.Thread(target=worker)
+        th.start()
+        start = time.perf_counter()
+        for t, r in zip(arrivals, reqs):
+            d = start + t - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            q.put((time.perf_counter(), r))
+        q.put(None)
+        th.join()
+        return np.array(lat) * 1e3
+
+    def run_server_at_rate():
+        srv.reset_stats()
+        ids = queue.Queue()
+
+        def waiter():
+            while True:
+                r = ids.get()
+                if r is None:
+                    return
+                srv.wait(r)
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        start = time.perf_counter()
+        for t, (p, s) in zip(arrivals, reqs):
+            d = start + t - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            ids.put(srv.submit(p, s.data, s.offsets))
+        ids.put(None)
+        th.join()
+        return srv.stats()
+
+    lp = run_plain_at_rate()
+    ss = run_server_at_rate()
+    srv.close()
+    return {
+        "requests": R,
+        "mb": round(total_bytes / 1e6, 1),
+        "plain_req_per_s": round(plain_cap, 1),
+        "batched_req_per_s": round(srv_cap, 1),
+        "throughput_ratio": round(srv_cap / plain_cap, 2),
+        "batched_GBs": round(total_bytes / (R / srv_cap) / 1e9, 3),
+        "rate_req_per_s": round(rate, 1),
+        "plain_p50_ms": round(float(np.percentile(lp, 50)), 3),
+        "plain_p99_ms": round(float(np.percentile(lp, 99)), 3),
+        "batched_p50_ms": round(ss["p50_us"] / 1e3, 3),
+        "batched_p99_ms": round(ss["p99_us"] / 1e3, 3),
+        "steps_at_capacity": int(st_cap["steps"]),
+        "graph_steps": int(st_cap["graph_steps"]),
+        "bit_exact": bool(exact),
+    }
 
 
 if __name__ == "__main__":

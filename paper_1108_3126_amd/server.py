@@ -60,10 +60,10 @@ class Server:
         return rid.value
 
     def wait(self, rid: int, timeout_us: int = -1) -> np.ndarray:
-        n = self._n[rid]
+        n = self._n.get(rid, 0)
         out = np.zeros(max(n, 1), np.uint8)
         rx._check(rx.lib().rx_server_wait(self._h, int(rid), out.ctypes.data, int(timeout_us)))
-        del self._n[rid]
+        self._n.pop(rid, None)
         return out[:n]
 
     def stats(self) -> dict:
