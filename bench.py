@@ -52,6 +52,7 @@ def main():
     ap.add_argument("--check", type=int, default=2000, help="sampled strings checked against the oracle")
     ap.add_argument("--serving", type=int, default=1000, help="requests in the serving comparison (0 = skip)")
     ap.add_argument("--copy-only", action="store_true", help="only run the stream-copy probe (counter calibration)")
+    ap.add_argument("--serving-only", action="store_true", help="only run the serving comparison")
     ap.add_argument("--copy-bytes", type=int, default=1 << 28)
     args = ap.parse_args()
 
@@ -69,6 +70,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.copy_only:
         print(json.dumps(copy_probe(torch, rx, dev, args.copy_bytes, reps=max(args.steps, 1))), flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps(run_serving(args, torch)), flush=True)
         return
     t0 = time.time()
     prog = W.single_program(1)
@@ -318,6 +322,8 @@ def run_serving(args, torch):
         "batched_p50_ms": round(ss["p50_us"] / 1e3, 3),
         "batched_p99_ms": round(ss["p99_us"] / 1e3, 3),
         "steps_at_capacity": int(st_cap["steps"]),
+        "capacity_pack_ms": round(st_cap["pack_ms"], 2),
+        "capacity_device_ms": round(st_cap["device_ms"], 2),
         "graph_steps": int(st_cap["graph_steps"]),
         "bit_exact": bool(exact),
     }

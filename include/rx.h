@@ -187,7 +187,8 @@ typedef struct {
     int32_t variant;        /* RX_VARIANT_* */
     int32_t block;          /* threads per workgroup (multiple of 64, <= 1024) */
     int32_t grid;           /* workgroups (0 = enough for one pass over the strings) */
-    int32_t unroll;         /* variant-specific inner unroll (sliced: bytes per load) */
+    int32_t unroll;         /* sliced: 1 = prefetch the next tile into registers while matching (default),
+                               2 = load each tile, then match it */
 } rx_launch;
 
 /* rx_match with an explicit kernel variant and launch shape (the autotuner's
@@ -322,6 +323,8 @@ typedef struct {
     int64_t cache_hits, cache_misses, cache_evictions;
     double p50_us, p99_us, mean_us, max_us; /* latency: submit -> results on the host */
     double wall_s;                          /* first submit -> last completion */
+    double pack_ms;                         /* scheduler time assembling and launching steps */
+    double device_ms;                       /* device time of steps (copies in, kernel, copy out) */
 } rx_server_counters;
 
 typedef struct rx_server rx_server;

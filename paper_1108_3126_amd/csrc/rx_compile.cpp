@@ -200,52 +200,100 @@ int compile(const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx_class*
     const int32_t W = (L + 1 + 31) / 32;
     P->W = W;
 
-    // A4: evolution of a single pointer: the leaves reachable by
-    // non-consuming moves (Fig. 4.2), with null recorded as the accept bit.
-    std::vector<uint32_t> stamp(m, 0);
-    uint32_t epoch = 0;
-    std::vector<int32_t> stack;
-    auto evolve_from = [&](int32_t start, uint32_t* set) {
-        ++epoch;
-        stack.clear();
-        stack.push_back(start);
-        while (!stack.empty()) {
-            const int32_t p = stack.back();
-            stack.pop_back();
-            if (p < 0) { set[L >> 5] |= 1u << (L & 31); continue; }
-            if (stamp[p] == epoch) continue;
-            stamp[p] = epoch;
-            switch (P->kind[p]) {
-            case RX_BYTE:
-            case RX_CLASS: {
-                const int32_t r = P->leaf_rank[p];
-                set[r >> 5] |= 1u << (r & 31);
-                break;
+    // A4: evolution of a single pointer (Def. 5.1 with null kept as the
+    // accept bit).  Entering node p reaches the leaves first(p) inside its
+    // subtree and, when p can be passed without consuming input (nullable),
+    // everything reached from cont p:
+    //     E(p) = first(p) OR (nullable(p) ? E(cont p) : 0),   E(null) = {accept}
+    // first/nullable are computed bottom-up (reverse breadth-first order puts
+    // children before parents); E is memoised along cont chains, which never
+    // cycle back to their start.  O(m * W) words.
+    std::vector<char> nu(m, 0);
+    std::vector<uint32_t> first_of((size_t)m * W, 0);
+    auto row = [&](std::vector<uint32_t>& v, int32_t p) { return &v[(size_t)p * W]; };
+    for (int32_t p = m - 1; p >= 0; --p) {
+        const int32_t a = P->c0[p], b = P->c1[p];
+        uint32_t* f = row(first_of, p);
+        switch (P->kind[p]) {
+        case RX_EPS: nu[p] = 1; break;
+        case RX_BYTE:
+        case RX_CLASS: {
+            const int32_t r = P->leaf_rank[p];
+            f[r >> 5] |= 1u << (r & 31);
+            break;
+        }
+        case RX_CAT:
+            nu[p] = nu[a] && nu[b];
+            for (int w = 0; w < W; ++w) f[w] = row(first_of, a)[w] | (nu[a] ? row(first_of, b)[w] : 0u);
+            break;
+        case RX_ALT:
+            nu[p] = nu[a] || nu[b];
+            for (int w = 0; w < W; ++w) f[w] = row(first_of, a)[w] | row(first_of, b)[w];
+            break;
+        case RX_STAR:
+        case RX_OPT:
+        case RX_PLUSLOOP:
+            nu[p] = 1;
+            for (int w = 0; w < W; ++w) f[w] = row(first_of, a)[w];
+            break;
+        case RX_PLUS:
+            nu[p] = nu[a];
+            for (int w = 0; w < W; ++w) f[w] = row(first_of, a)[w];
+            break;
+        default: break;
+        }
+    }
+    // PLUS companions sit after the tree in d[] but read their child's first
+    // set, which the loop above filled before reaching them only if the child
+    // index is larger; recompute them now that every tree node is done.
+    for (int32_t p = nt; p < m; ++p)
+        for (int w = 0; w < W; ++w) row(first_of, p)[w] = row(first_of, P->c0[p])[w];
+    std::vector<uint32_t> E((size_t)m * W, 0);
+    std::vector<char> have(m, 0);
+    std::vector<int32_t> chain;
+    auto evolve_into = [&](int32_t q, uint32_t* out) {
+        // walk q, cont q, ... while nullable, then fold the first sets back
+        chain.clear();
+        int32_t p = q;
+        while (p >= 0 && !have[p]) {
+            chain.push_back(p);
+            if (!nu[p]) break;
+            p = P->cont[p];
+        }
+        for (size_t k = chain.size(); k-- > 0;) {
+            const int32_t c = chain[k];
+            uint32_t* e = row(E, c);
+            const uint32_t* f = row(first_of, c);
+            for (int w = 0; w < W; ++w) e[w] = f[w];
+            if (nu[c]) {
+                const int32_t nx = P->cont[c];
+                if (nx < 0) e[L >> 5] |= 1u << (L & 31);
+                else
+                    for (int w = 0; w < W; ++w) e[w] |= row(E, nx)[w];
             }
-            case RX_ALT: stack.push_back(P->c0[p]); stack.push_back(P->c1[p]); break;
-            case RX_CAT: stack.push_back(P->c0[p]); break;
-            case RX_STAR:
-            case RX_OPT:
-            case RX_PLUSLOOP: stack.push_back(P->c0[p]); stack.push_back(P->cont[p]); break;
-            case RX_PLUS: stack.push_back(P->c0[p]); break;
-            case RX_EPS: stack.push_back(P->cont[p]); break;
-            default: break;
-            }
+            have[c] = 1;
+        }
+        if (q < 0) {
+            for (int w = 0; w < W; ++w) out[w] = 0;
+            out[L >> 5] |= 1u << (L & 31);
+        } else {
+            for (int w = 0; w < W; ++w) out[w] = row(E, q)[w];
         }
     };
     P->first.assign(W, 0);
-    evolve_from(0, P->first.data());
+    evolve_into(0, P->first.data());
     P->follow.assign((size_t)L * W, 0);
-    for (int32_t r = 0; r < L; ++r) evolve_from(P->cont[P->leaf_node[r]], &P->follow[(size_t)r * W]);
+    for (int32_t r = 0; r < L; ++r) evolve_into(P->cont[P->leaf_node[r]], &P->follow[(size_t)r * W]);
     P->bytemask.assign((size_t)256 * W, 0);
     for (int32_t r = 0; r < L; ++r) {
         const int32_t p = P->leaf_node[r];
-        for (int b = 0; b < 256; ++b) {
-            bool hit;
-            if (P->kind[p] == RX_BYTE) hit = P->label[p] == b;
-            else hit = (P->classes[P->label[p]][b >> 6] >> (b & 63)) & 1;
-            if (hit) P->bytemask[(size_t)b * W + (r >> 5)] |= 1u << (r & 31);
+        if (P->kind[p] == RX_BYTE) {
+            P->bytemask[(size_t)P->label[p] * W + (r >> 5)] |= 1u << (r & 31);
+            continue;
         }
+        const auto& c = P->classes[P->label[p]];
+        for (int b = 0; b < 256; ++b)
+            if ((c[b >> 6] >> (b & 63)) & 1) P->bytemask[(size_t)b * W + (r >> 5)] |= 1u << (r & 31);
     }
     P->nullable = (P->first[L >> 5] >> (L & 31)) & 1;
     // (e)(any)*: once the accept bit is set it stays set

@@ -151,7 +151,7 @@ int jit_compile(Program* P, const char* arch);
 void jit_free(Program* P);
 bool jit_ready(const Program* P, int* n_state, int* n_ops);
 int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,
-                        void* stream);
+                        int burst, void* stream);
 int launch_wave(const LaunchArgs& a);
 const char* hip_error_string(int err);
 int launch_stream_copy(void* dst, const void* src, int64_t bytes, void* stream);

@@ -278,7 +278,7 @@ std::string jit_step_source(const Program& P, int* n_state, int* n_ops) {
 // 32x32 bit transpose: afterwards a[k] bit j == (before) a[j] bit k.  The two
 // byte-granular stages are byte permutes (v_perm_b32, one instruction per
 // word); the three bit stages are a shift plus a bit-field insert per word.
-const char* kTransposeSource = R"(
+const char* kTransposeSource = R"RX(
 #ifndef RX_PERM
 #define RX_PERM(hi, lo, sel) __builtin_amdgcn_perm((hi), (lo), (sel))
 #endif
@@ -309,20 +309,46 @@ __device__ __forceinline__ void rx_transpose32(u32 (&a)[32]) {
         }
     }
 }
-)";
+)RX";
 
 // Fixed-length strings: string i is bytes[i*length, (i+1)*length).  One
 // wavefront runs 2048 strings: lane l owns bit j of every word for string
 // base + 64 j + l.  32-byte tiles of every string are staged in LDS by
 // asynchronous 16-byte global->LDS loads, then each lane reads 4 bytes of its
 // 32 strings, transposes them into bit planes and runs four macro steps.
-const char* kFixedKernelSource = R"(
+const char* kFixedKernelSource = R"RX(
 // ---- device kernel ----
 typedef __attribute__((address_space(1))) void rx_gvoid;
 typedef __attribute__((address_space(3))) void rx_lvoid;
+typedef __attribute__((address_space(3))) u32 rx_lds_u32;
+typedef unsigned int rx_v4 __attribute__((ext_vector_type(4)));
 #define RX_WAVE_STRINGS 2048
 #define RX_TILE 32
 
+// Runs the macro step over positions [0, np) of the staged 32-byte tile.
+__device__ __forceinline__ void rx_run_tile(const u32* rx_tile, int lane, int np, u32 (&s)[RX_NS], u32& acc) {
+    for (int pq = 0; pq < np; pq += 4) {
+        u32 w[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) w[j] = rx_tile[(j * 64 + lane) * 8 + (pq >> 2)];
+        rx_transpose32(w);
+        rx_step(s, acc, w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7]);
+        if (pq + 1 < np) rx_step(s, acc, w[8], w[9], w[10], w[11], w[12], w[13], w[14], w[15]);
+        if (pq + 2 < np) rx_step(s, acc, w[16], w[17], w[18], w[19], w[20], w[21], w[22], w[23]);
+        if (pq + 3 < np) rx_step(s, acc, w[24], w[25], w[26], w[27], w[28], w[29], w[30], w[31]);
+    }
+}
+
+__device__ __forceinline__ void rx_store_result(unsigned char* __restrict__ out, long long base, long long n, int lane,
+                                                 u32 acc) {
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        const long long sid = base + j * 64 + lane;
+        if (sid < n) out[sid] = (unsigned char)((acc >> j) & 1u);
+    }
+}
+
+// 32-byte bursts: each tile is fetched straight into LDS.
 extern "C" __global__ __launch_bounds__(64, 1) void rx_sliced_fixed(const unsigned char* __restrict__ bytes,
         long long length, long long n, unsigned char* __restrict__ out) {
     extern __shared__ u32 rx_tile[];   // RX_WAVE_STRINGS * RX_TILE bytes
@@ -346,29 +372,62 @@ extern "C" __global__ __launch_bounds__(64, 1) void rx_sliced_fixed(const unsign
         }
         __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the tile has landed
         const long long left = length - t * RX_TILE;
-        const int np = left < RX_TILE ? (int)left : RX_TILE;
-        for (int pq = 0; pq < np; pq += 4) {
-            u32 w[32];
-#pragma unroll
-            for (int j = 0; j < 32; ++j) w[j] = rx_tile[(j * 64 + lane) * 8 + (pq >> 2)];
-            rx_transpose32(w);
-            rx_step(s, acc, w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7]);
-            if (pq + 1 < np) rx_step(s, acc, w[8], w[9], w[10], w[11], w[12], w[13], w[14], w[15]);
-            if (pq + 2 < np) rx_step(s, acc, w[16], w[17], w[18], w[19], w[20], w[21], w[22], w[23]);
-            if (pq + 3 < np) rx_step(s, acc, w[24], w[25], w[26], w[27], w[28], w[29], w[30], w[31]);
-        }
+        rx_run_tile(rx_tile, lane, left < RX_TILE ? (int)left : RX_TILE, s, acc);
     }
+    rx_store_result(out, base, n, lane, acc);
+}
+
+// Prefetching: the next 32-byte tile of every string streams into
+// accumulation registers (unused by this kernel otherwise) while the current
+// tile is matched from LDS, so load latency hides behind the circuit.
+// At a tile boundary the registers are written to LDS and the following
+// tile's loads are issued before matching starts.
+__device__ __forceinline__ void rx_issue_tile(const unsigned char* __restrict__ bytes, long long length, long long n,
+                                              long long base, int lane, long long t, rx_v4 (&nx)[RX_WAVE_STRINGS / 32]) {
+    long long off = t * RX_TILE + 16 * (lane & 1);
+    if (off >= length) off = t * RX_TILE;   // past a string's end: an in-bounds duplicate, never matched
 #pragma unroll
-    for (int j = 0; j < 32; ++j) {
-        const long long sid = base + j * 64 + lane;
-        if (sid < n) out[sid] = (unsigned char)((acc >> j) & 1u);
+    for (int q = 0; q < RX_WAVE_STRINGS / 32; ++q) {
+        long long sid = base + q * 32 + (lane >> 1);
+        if (sid > n - 1) sid = n - 1;
+        const unsigned char* p = bytes + sid * length + off;
+        asm volatile("global_load_dwordx4 %0, %1, off" : "=a"(nx[q]) : "v"(p) : "memory");
     }
 }
-)";
+
+extern "C" __global__ __launch_bounds__(64, 1) void rx_sliced_fixed_pf(const unsigned char* __restrict__ bytes,
+        long long length, long long n, unsigned char* __restrict__ out) {
+    extern __shared__ u32 rx_tile[];
+    const int lane = threadIdx.x;
+    const long long base = (long long)blockIdx.x * RX_WAVE_STRINGS;
+    u32 s[RX_NS];
+    u32 acc;
+    rx_init(s, acc);
+    const long long ntiles = (length + RX_TILE - 1) / RX_TILE;
+    rx_v4 nx[RX_WAVE_STRINGS / 32];
+    rx_issue_tile(bytes, length, n, base, lane, 0, nx);
+    for (long long t = 0; t < ntiles; ++t) {
+        // tile t has landed in registers; the previous tile's LDS reads are done
+        asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+#pragma unroll
+        for (int q = 0; q < RX_WAVE_STRINGS / 32; ++q) {
+            const u32 a = (u32)(unsigned long long)(rx_lds_u32*)(rx_tile + q * 256 + 4 * lane);
+            asm volatile("ds_write_b128 %0, %1" ::"v"(a), "a"(nx[q]) : "memory");
+        }
+        // the writes have read their registers before the next loads refill them
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        if (t + 1 < ntiles) rx_issue_tile(bytes, length, n, base, lane, t + 1, nx);
+        const long long left = length - t * RX_TILE;
+        rx_run_tile(rx_tile, lane, left < RX_TILE ? (int)left : RX_TILE, s, acc);
+    }
+    rx_store_result(out, base, n, lane, acc);
+}
+)RX";
 
 struct JitKernel {
     hipModule_t mod = nullptr;
     hipFunction_t fixed = nullptr;
+    hipFunction_t fixed64 = nullptr;
     int dev = -1;
     int n_state = 0, n_ops = 0;
     std::string arch;
@@ -426,6 +485,7 @@ int jit_compile(Program* P, const char* arch_in) {
         hipError_t e = hipModuleLoadData(&K->mod, code.data());
         if (e != hipSuccess) { delete K; return fail(RX_EHIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e)); }
         e = hipModuleGetFunction(&K->fixed, K->mod, "rx_sliced_fixed");
+        if (e == hipSuccess) e = hipModuleGetFunction(&K->fixed64, K->mod, "rx_sliced_fixed_pf");
         if (e != hipSuccess) {
             hipModuleUnload(K->mod);
             delete K;
@@ -454,16 +514,17 @@ bool jit_ready(const Program* P, int* n_state, int* n_ops) {
 }
 
 int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,
-                        void* stream) {
+                        int burst, void* stream) {
     const JitKernel* K = static_cast<const JitKernel*>(P->jit);
-    if (!K || !K->fixed) return (int)hipErrorInvalidValue;
+    if (!K || !K->fixed || !K->fixed64) return (int)hipErrorInvalidValue;
+    hipFunction_t fn = burst == 1 ? K->fixed64 : K->fixed;
     const long long grid = (n + 2047) / 2048;
     const unsigned lds = 2048 * 32;
     long long len = length, nn = n;
     const void* b = bytes;
     void* o = out;
     void* args[] = {&b, &len, &nn, &o};
-    return (int)hipModuleLaunchKernel(K->fixed, (unsigned)grid, 1, 1, 64, 1, 1, lds, (hipStream_t)stream, args, nullptr);
+    return (int)hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, 64, 1, 1, lds, (hipStream_t)stream, args, nullptr);
 }
 
 }  // namespace rx

@@ -61,11 +61,21 @@ __device__ __forceinline__ void lane_step(uint32_t (&S)[W], uint32_t c, const ui
     for (int w = 0; w < W; ++w) {
         uint32_t x = X[w];
         while (x) {
-            const int b = __builtin_ctz(x);
+            // up to four survivors per round: their rows are fetched together
+            const int b0 = __builtin_ctz(x);
             x &= x - 1;
-            const uint32_t* row = F + (w * 32 + b) * W;
+            const int b1 = x ? __builtin_ctz(x) : b0;
+            x &= x - 1;
+            const int b2 = x ? __builtin_ctz(x) : b0;
+            x &= x - 1;
+            const int b3 = x ? __builtin_ctz(x) : b0;
+            x &= x - 1;
+            const uint32_t* r0 = F + (w * 32 + b0) * W;
+            const uint32_t* r1 = F + (w * 32 + b1) * W;
+            const uint32_t* r2 = F + (w * 32 + b2) * W;
+            const uint32_t* r3 = F + (w * 32 + b3) * W;
 #pragma unroll
-            for (int v = 0; v < W; ++v) S[v] |= row[v];
+            for (int v = 0; v < W; ++v) S[v] |= (r0[v] | r1[v]) | (r2[v] | r3[v]);
         }
     }
 }

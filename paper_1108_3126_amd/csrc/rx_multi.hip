@@ -35,32 +35,45 @@ struct ItemKArgs {
     uint8_t* out;
 };
 
-__device__ __forceinline__ void step_rt(uint32_t (&S)[kWMax], int W, uint32_t c, const uint32_t* __restrict__ M,
-                                        const uint32_t* __restrict__ F) {
-    uint32_t X[kWMax];
+// One macro step on a W-word set: survivors X = S & M[c]; S' = OR of their
+// Follow rows.  Up to four survivors are taken per round so their rows are
+// fetched from LDS together (a repeated row is harmless under OR).
+template <int W>
+__device__ __forceinline__ void step_w(uint32_t (&S)[W], uint32_t c, const uint32_t* __restrict__ M,
+                                       const uint32_t* __restrict__ F) {
+    uint32_t X[W];
 #pragma unroll
-    for (int w = 0; w < kWMax; ++w) X[w] = w < W ? (S[w] & M[c * W + w]) : 0u;
+    for (int w = 0; w < W; ++w) X[w] = S[w] & M[c * W + w];
 #pragma unroll
-    for (int w = 0; w < kWMax; ++w) S[w] = 0;
+    for (int w = 0; w < W; ++w) S[w] = 0;
 #pragma unroll
-    for (int w = 0; w < kWMax; ++w) {
+    for (int w = 0; w < W; ++w) {
         uint32_t x = X[w];
         while (x) {
-            const int b = __builtin_ctz(x);
+            const int b0 = __builtin_ctz(x);
             x &= x - 1;
-            const uint32_t* row = F + (w * 32 + b) * W;
+            const int b1 = x ? __builtin_ctz(x) : b0;
+            x &= x - 1;
+            const int b2 = x ? __builtin_ctz(x) : b0;
+            x &= x - 1;
+            const int b3 = x ? __builtin_ctz(x) : b0;
+            x &= x - 1;
+            const uint32_t* r0 = F + (w * 32 + b0) * W;
+            const uint32_t* r1 = F + (w * 32 + b1) * W;
+            const uint32_t* r2 = F + (w * 32 + b2) * W;
+            const uint32_t* r3 = F + (w * 32 + b3) * W;
 #pragma unroll
-            for (int v = 0; v < kWMax; ++v)
-                if (v < W) S[v] |= row[v];
+            for (int v = 0; v < W; ++v) S[v] |= (r0[v] | r1[v]) | (r2[v] | r3[v]);
         }
     }
 }
 
-__device__ int match_one(const uint32_t* __restrict__ first, const uint32_t* M, const uint32_t* F, int L, int W,
-                         int suffix_any, const uint8_t* __restrict__ bytes, int64_t lo, int64_t hi) {
-    uint32_t S[kWMax];
+template <int W>
+__device__ int match_w(const uint32_t* __restrict__ first, const uint32_t* M, const uint32_t* F, int L,
+                       int suffix_any, const uint8_t* __restrict__ bytes, int64_t lo, int64_t hi) {
+    uint32_t S[W];
 #pragma unroll
-    for (int w = 0; w < kWMax; ++w) S[w] = w < W ? first[w] : 0u;
+    for (int w = 0; w < W; ++w) S[w] = first[w];
     const int aw = L >> 5;
     const uint32_t abit = 1u << (L & 31);
     const int64_t skew = (int64_t)(reinterpret_cast<uintptr_t>(bytes) & 15);
@@ -71,10 +84,10 @@ __device__ int match_one(const uint32_t* __restrict__ first, const uint32_t* M, 
         const int b1 = hi - base < 16 ? (int)(hi - base) : 16;
 #pragma unroll
         for (int b = 0; b < 16; ++b)
-            if (b >= b0 && b < b1) step_rt(S, W, (wv[b >> 2] >> (8 * (b & 3))) & 255u, M, F);
+            if (b >= b0 && b < b1) step_w<W>(S, (wv[b >> 2] >> (8 * (b & 3))) & 255u, M, F);
         uint32_t any = 0, acc = 0;
 #pragma unroll
-        for (int w = 0; w < kWMax; ++w) {
+        for (int w = 0; w < W; ++w) {
             any |= S[w];
             acc |= (w == aw) ? S[w] : 0u;
         }
@@ -83,8 +96,20 @@ __device__ int match_one(const uint32_t* __restrict__ first, const uint32_t* M, 
     }
     uint32_t acc = 0;
 #pragma unroll
-    for (int w = 0; w < kWMax; ++w) acc |= (w == aw) ? S[w] : 0u;
+    for (int w = 0; w < W; ++w) acc |= (w == aw) ? S[w] : 0u;
     return (acc & abit) ? 1 : 0;
+}
+
+__device__ int match_one(const uint32_t* __restrict__ first, const uint32_t* M, const uint32_t* F, int L, int W,
+                         int suffix_any, const uint8_t* __restrict__ bytes, int64_t lo, int64_t hi) {
+    switch (W) {
+#define RX_MW(w) \
+    case w: return match_w<w>(first, M, F, L, suffix_any, bytes, lo, hi);
+        RX_MW(1) RX_MW(2) RX_MW(3) RX_MW(4) RX_MW(5) RX_MW(6) RX_MW(7) RX_MW(8)
+        RX_MW(9) RX_MW(10) RX_MW(11) RX_MW(12) RX_MW(13) RX_MW(14) RX_MW(15) RX_MW(16)
+#undef RX_MW
+    default: return 0;  // not reached: the host refuses programs above 16 words
+    }
 }
 
 __global__ __launch_bounds__(256) void k_items(ItemKArgs a) {

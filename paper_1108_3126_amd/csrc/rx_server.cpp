@@ -59,6 +59,7 @@ struct Request {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done_ev = nullptr;
+    hipEvent_t start_ev = nullptr;
     uint8_t *h_bytes = nullptr, *h_out = nullptr, *h_items = nullptr;
     int64_t* h_offs = nullptr;
     uint8_t *d_bytes = nullptr, *d_out = nullptr, *d_items = nullptr;
@@ -94,6 +95,7 @@ struct Server {
     std::vector<double> lat_us;
     int64_t submitted = 0, completed = 0, rejected = 0, steps = 0, graph_steps = 0, strings = 0, bytes = 0;
     int64_t hits = 0, misses = 0, evictions = 0, max_queue = 0;
+    double pack_ms = 0, device_ms = 0;
     bool have_first = false;
     Clock::time_point t_first, t_last;
 
@@ -122,7 +124,8 @@ int Server::init() {
         const size_t nb = (size_t)cfg.step_bytes + 16, no = 8 * (size_t)(cfg.step_strings + 1),
                      ni = kItemHeader + sizeof(WorkItem) * (size_t)max_items, nr = (size_t)cfg.step_strings;
         hipError_t e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
-        if (!e) e = hipEventCreateWithFlags(&s.done_ev, hipEventDisableTiming);
+        if (!e) e = hipEventCreate(&s.done_ev);
+        if (!e) e = hipEventCreate(&s.start_ev);
         if (!e) e = hipHostMalloc((void**)&s.h_bytes, nb, hipHostMallocDefault);
         if (!e) e = hipHostMalloc((void**)&s.h_offs, no, hipHostMallocDefault);
         if (!e) e = hipHostMalloc((void**)&s.h_items, ni, hipHostMallocDefault);
@@ -145,6 +148,7 @@ Server::~Server() {
         if (s.stream) hipStreamSynchronize(s.stream);
         step_graph_destroy(s.graph);
         if (s.done_ev) hipEventDestroy(s.done_ev);
+        if (s.start_ev) hipEventDestroy(s.start_ev);
         if (s.stream) hipStreamDestroy(s.stream);
         hipHostFree(s.h_bytes);
         hipHostFree(s.h_offs);
@@ -193,7 +197,9 @@ int Server::ensure_resident(CacheEntry* e, Slot& s) {
 }
 
 bool Server::launch_step(Slot& s, std::vector<Request*>& take) {
+    const Clock::time_point t0 = Clock::now();
     ++step_seq;
+    hipEventRecord(s.start_ev, s.stream);
     s.reqs = take;
     s.line0.clear();
     s.entries.clear();
@@ -283,12 +289,16 @@ bool Server::launch_step(Slot& s, std::vector<Request*>& take) {
     }
     s.busy = true;
     ++steps;
+    pack_ms += std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
     return true;
 }
 
 void Server::complete(Slot& s) {
     const Clock::time_point now = Clock::now();
+    float dev_ms = 0;
+    hipEventElapsedTime(&dev_ms, s.start_ev, s.done_ev);
     std::lock_guard<std::mutex> g(mu);
+    device_ms += dev_ms;
     for (size_t i = 0; i < s.reqs.size(); ++i) {
         Request* r = s.reqs[i];
         r->result.assign(s.h_out + s.line0[i], s.h_out + s.line0[i] + r->n);
@@ -541,6 +551,8 @@ int rx_server_stats(rx_server* srv, rx_server_counters* out) {
     out->cache_evictions = S->evictions;
     out->max_queue = S->max_queue;
     out->queued = (int64_t)S->pending.size();
+    out->pack_ms = S->pack_ms;
+    out->device_ms = S->device_ms;
     if (!S->lat_us.empty()) {
         std::vector<double> v = S->lat_us;
         std::sort(v.begin(), v.end());
@@ -564,6 +576,7 @@ int rx_server_reset_stats(rx_server* srv) {
     S->lat_us.clear();
     S->submitted = S->completed = S->rejected = S->steps = S->graph_steps = S->strings = S->bytes = 0;
     S->hits = S->misses = S->evictions = S->max_queue = 0;
+    S->pack_ms = S->device_ms = 0;
     S->have_first = false;
     return RX_OK;
 }

@@ -71,7 +71,8 @@ class rx_server_counters(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "rejected", "queued", "max_queue", "steps",
                                                "graph_steps", "strings", "bytes", "cache_hits", "cache_misses",
                                                "cache_evictions")] + \
-               [(k, ctypes.c_double) for k in ("p50_us", "p99_us", "mean_us", "max_us", "wall_s")]
+               [(k, ctypes.c_double) for k in ("p50_us", "p99_us", "mean_us", "max_us", "wall_s", "pack_ms",
+                                                "device_ms")]
 
 
 class rx_launch(ctypes.Structure):

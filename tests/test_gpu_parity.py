@@ -165,11 +165,11 @@ def test_pathological_4096_nodes(dev, family, k):
 # ---------------------------------------------------------------------------
 # bit-sliced circuit kernel (fixed-length strings)
 # ---------------------------------------------------------------------------
-def fixed_match(p, s, length, dev, variant=0):
+def fixed_match(p, s, length, dev, variant=0, burst=0):
     from paper_1108_3126_amd import rx
 
     d = torch.from_numpy(s.data if s.data.size else np.zeros(16, np.uint8)).to(dev)
-    out = rx.match_fixed(p, d, length, s.n, launch=(variant, 0, 0, 0) if variant else None)
+    out = rx.match_fixed(p, d, length, s.n, launch=(variant, 0, 0, burst) if variant else None)
     torch.cuda.synchronize()
     return out.cpu().numpy()
 
@@ -185,10 +185,12 @@ def test_sliced_single_program(dev):
     print("sliced single: accepted", int(want.sum()), flush=True)
     for v in (rx.VARIANT_SLICED, rx.VARIANT_LANE, rx.VARIANT_WAVE, 0):
         assert np.array_equal(fixed_match(p, s, 256, dev, v), want), v
+    assert np.array_equal(fixed_match(p, s, 256, dev, rx.VARIANT_SLICED, 2), want)
 
 
-@pytest.mark.parametrize("length", [16, 32, 48, 80, 272])
-def test_sliced_lengths_and_counts(dev, length):
+@pytest.mark.parametrize("burst", [1, 2])
+@pytest.mark.parametrize("length", [16, 32, 48, 64, 80, 112, 272])
+def test_sliced_lengths_and_counts(dev, length, burst):
     from paper_1108_3126_amd import rx
 
     rng = np.random.default_rng(length)
@@ -197,7 +199,7 @@ def test_sliced_lengths_and_counts(dev, length):
         s, _ = W.single_strings(prog, seed=length + n, n=n, length=length, plant_frac=0.3)
         p = rx.compile(prog.ast, prog.root, prog.classes, True).upload(dev).jit()
         want = oracle_match(prog, s)
-        assert np.array_equal(fixed_match(p, s, length, dev, rx.VARIANT_SLICED), want), (length, n)
+        assert np.array_equal(fixed_match(p, s, length, dev, rx.VARIANT_SLICED, burst), want), (length, n)
 
 
 @pytest.mark.parametrize("seed", range(6))
