@@ -187,8 +187,8 @@ typedef struct {
     int32_t variant;        /* RX_VARIANT_* */
     int32_t block;          /* threads per workgroup (multiple of 64, <= 1024) */
     int32_t grid;           /* workgroups (0 = enough for one pass over the strings) */
-    int32_t unroll;         /* sliced: 1 = prefetch the next tile into registers while matching (default),
-                               2 = load each tile, then match it */
+    int32_t unroll;         /* sliced: 1 = prefetch the next tile into registers while matching,
+                               2 = load each tile, then match it, 3 = a loader wave fetches 64-byte bursts (default) */
 } rx_launch;
 
 /* rx_match with an explicit kernel variant and launch shape (the autotuner's

@@ -231,9 +231,10 @@ int rx_match_fixed_ex(const rx_program* prog, const uint8_t* d_bytes, int64_t le
         {
             int dev = -1;
             hip_current_device(&dev);
-            if (a.unroll != 0 && a.unroll != 1 && a.unroll != 2)
-                return fail(RX_EINVAL, "sliced kernel staging (unroll) must be 1 (prefetch) or 2 (load then match)");
-            e = launch_sliced_fixed(P, d_bytes, length, n, d_out, a.unroll ? a.unroll : 1, stream);
+            if (a.unroll < 0 || a.unroll > 3)
+                return fail(RX_EINVAL, "sliced kernel staging (unroll) must be 1 (prefetch), 2 (load then match) "
+                                       "or 3 (loader wave)");
+            e = launch_sliced_fixed(P, d_bytes, length, n, d_out, a.unroll ? a.unroll : 3, stream);
         }
         break;
     case RX_VARIANT_LANE:

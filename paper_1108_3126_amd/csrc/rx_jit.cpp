@@ -282,6 +282,12 @@ const char* kTransposeSource = R"RX(
 #ifndef RX_PERM
 #define RX_PERM(hi, lo, sel) __builtin_amdgcn_perm((hi), (lo), (sel))
 #endif
+// bit select (a & m) | (b & ~m) as one 3-input bit operation; the table
+// 0xE4 is that function evaluated on the operand patterns a = 0xF0,
+// b = 0xCC, m = 0xAA
+#ifndef RX_SEL
+#define RX_SEL(a, b, m) __builtin_amdgcn_bitop3_b32((a), (b), (m), 0xE4)
+#endif
 __device__ __forceinline__ void rx_transpose32(u32 (&a)[32]) {
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
@@ -303,8 +309,8 @@ __device__ __forceinline__ void rx_transpose32(u32 (&a)[32]) {
         for (unsigned j = 0; j < 32; ++j) {
             if ((j & d) == 0) {
                 const u32 x = a[j], y = a[j + d];
-                a[j] = (x & m) | ((y << d) & ~m);
-                a[j + d] = ((x >> d) & m) | (y & ~m);
+                a[j] = RX_SEL(x, y << d, m);
+                a[j + d] = RX_SEL(x >> d, y, m);
             }
         }
     }
@@ -395,6 +401,63 @@ __device__ __forceinline__ void rx_issue_tile(const unsigned char* __restrict__ 
     }
 }
 
+// Two waves per workgroup: every string's next 64 bytes are requested as one
+// burst, its first 32 bytes by the matching wave (into accumulation
+// registers) and its second 32 by a loader wave (into its registers), so a
+// cache line is fetched in two halves at about the same time instead of four
+// quarters a tile apart.  The halves are written to LDS in turn; the next
+// burst is in flight while the matching wave works on the second half.
+__device__ __forceinline__ void rx_issue_half(const unsigned char* __restrict__ bytes, long long length, long long n,
+                                              long long base, int lane, long long off_half,
+                                              rx_v4 (&nx)[RX_WAVE_STRINGS / 32]) {
+    long long off = off_half + 16 * (lane & 1);
+    if (off >= length) off = length - 16;   // past a string's end: an in-bounds duplicate, never matched
+#pragma unroll
+    for (int q = 0; q < RX_WAVE_STRINGS / 32; ++q) {
+        long long sid = base + q * 32 + (lane >> 1);
+        if (sid > n - 1) sid = n - 1;
+        const unsigned char* p = bytes + sid * length + off;
+        asm volatile("global_load_dwordx4 %0, %1, off" : "=a"(nx[q]) : "v"(p) : "memory");
+    }
+}
+
+__device__ __forceinline__ void rx_regs_to_tile(u32* rx_tile, int lane, rx_v4 (&nx)[RX_WAVE_STRINGS / 32]) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+#pragma unroll
+    for (int q = 0; q < RX_WAVE_STRINGS / 32; ++q) {
+        const u32 a = (u32)(unsigned long long)(rx_lds_u32*)(rx_tile + q * 256 + 4 * lane);
+        asm volatile("ds_write_b128 %0, %1" ::"v"(a), "a"(nx[q]) : "memory");
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_duo(const unsigned char* __restrict__ bytes,
+        long long length, long long n, unsigned char* __restrict__ out) {
+    extern __shared__ u32 rx_tile[];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const long long base = (long long)blockIdx.x * RX_WAVE_STRINGS;
+    u32 s[RX_NS];
+    u32 acc;
+    rx_init(s, acc);
+    const long long nbursts = (length + 63) / 64;
+    const long long nhalves = (length + 31) / 32;
+    rx_v4 nx[RX_WAVE_STRINGS / 32];
+    rx_issue_half(bytes, length, n, base, lane, wave * 32, nx);
+    for (long long h = 0; h < nhalves; ++h) {
+        const long long k = h >> 1;
+        const int half = (int)(h & 1);
+        if (wave == half) rx_regs_to_tile(rx_tile, lane, nx);   // this half of burst k
+        __syncthreads();
+        if (half == 1 && k + 1 < nbursts) rx_issue_half(bytes, length, n, base, lane, (k + 1) * 64 + wave * 32, nx);
+        const long long left = length - h * 32;
+        if (wave == 0) rx_run_tile(rx_tile, lane, left < 32 ? (int)left : 32, s, acc);
+        __syncthreads();
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // a trailing half that was never matched has landed
+    if (wave == 0) rx_store_result(out, base, n, lane, acc);
+}
+
 extern "C" __global__ __launch_bounds__(64, 1) void rx_sliced_fixed_pf(const unsigned char* __restrict__ bytes,
         long long length, long long n, unsigned char* __restrict__ out) {
     extern __shared__ u32 rx_tile[];
@@ -428,6 +491,7 @@ struct JitKernel {
     hipModule_t mod = nullptr;
     hipFunction_t fixed = nullptr;
     hipFunction_t fixed64 = nullptr;
+    hipFunction_t duo = nullptr;
     int dev = -1;
     int n_state = 0, n_ops = 0;
     std::string arch;
@@ -486,6 +550,7 @@ int jit_compile(Program* P, const char* arch_in) {
         if (e != hipSuccess) { delete K; return fail(RX_EHIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e)); }
         e = hipModuleGetFunction(&K->fixed, K->mod, "rx_sliced_fixed");
         if (e == hipSuccess) e = hipModuleGetFunction(&K->fixed64, K->mod, "rx_sliced_fixed_pf");
+        if (e == hipSuccess) e = hipModuleGetFunction(&K->duo, K->mod, "rx_sliced_fixed_duo");
         if (e != hipSuccess) {
             hipModuleUnload(K->mod);
             delete K;
@@ -516,15 +581,16 @@ bool jit_ready(const Program* P, int* n_state, int* n_ops) {
 int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,
                         int burst, void* stream) {
     const JitKernel* K = static_cast<const JitKernel*>(P->jit);
-    if (!K || !K->fixed || !K->fixed64) return (int)hipErrorInvalidValue;
-    hipFunction_t fn = burst == 1 ? K->fixed64 : K->fixed;
+    if (!K || !K->fixed || !K->fixed64 || !K->duo) return (int)hipErrorInvalidValue;
+    hipFunction_t fn = burst == 1 ? K->fixed64 : burst == 3 ? K->duo : K->fixed;
+    const unsigned threads = burst == 3 ? 128 : 64;
     const long long grid = (n + 2047) / 2048;
     const unsigned lds = 2048 * 32;
     long long len = length, nn = n;
     const void* b = bytes;
     void* o = out;
     void* args[] = {&b, &len, &nn, &o};
-    return (int)hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, 64, 1, 1, lds, (hipStream_t)stream, args, nullptr);
+    return (int)hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, threads, 1, 1, lds, (hipStream_t)stream, args, nullptr);
 }
 
 }  // namespace rx

@@ -186,9 +186,10 @@ def test_sliced_single_program(dev):
     for v in (rx.VARIANT_SLICED, rx.VARIANT_LANE, rx.VARIANT_WAVE, 0):
         assert np.array_equal(fixed_match(p, s, 256, dev, v), want), v
     assert np.array_equal(fixed_match(p, s, 256, dev, rx.VARIANT_SLICED, 2), want)
+    assert np.array_equal(fixed_match(p, s, 256, dev, rx.VARIANT_SLICED, 3), want)
 
 
-@pytest.mark.parametrize("burst", [1, 2])
+@pytest.mark.parametrize("burst", [1, 2, 3])
 @pytest.mark.parametrize("length", [16, 32, 48, 64, 80, 112, 272])
 def test_sliced_lengths_and_counts(dev, length, burst):
     from paper_1108_3126_amd import rx

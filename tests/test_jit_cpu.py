@@ -23,6 +23,7 @@ static inline unsigned rx_perm_cpu(unsigned hi, unsigned lo, unsigned sel) {
     return r;
 }
 #define RX_PERM(hi, lo, sel) rx_perm_cpu((hi), (lo), (sel))
+#define RX_SEL(a, b, m) ((((unsigned)(a)) & (m)) | (((unsigned)(b)) & ~(m)))
 """
 
 DRIVER = r"""
