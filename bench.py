@@ -25,6 +25,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_id(p, launch_desc: str) -> str:
+    """Identity of the timed kernel: its generated source and launch variant."""
+    import hashlib
+
+    src = p.jit_source() if p.jit_stats()["ready"] else "table-form"
+    return hashlib.sha256((src + "|" + launch_desc).encode()).hexdigest()[:16]
+
+
+def recorded_traffic(kid: str):
+    """HBM bytes per launch measured with rocprofv3 PMC counters for this exact kernel, or None."""
+    if not os.path.isdir(PROFILES):
+        return None
+    for name in sorted(os.listdir(PROFILES)):
+        if not name.endswith(".txt"):
+            continue
+        fields = {}
+        for line in open(os.path.join(PROFILES, name)):
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        if fields.get("kernel_id") == kid and "traffic_bytes_per_launch" in fields:
+            return int(fields["traffic_bytes_per_launch"])
+    return None
 
 
 def log(*a):
@@ -53,6 +79,9 @@ def main():
     ap.add_argument("--serving", type=int, default=1000, help="requests in the serving comparison (0 = skip)")
     ap.add_argument("--copy-only", action="store_true", help="only run the stream-copy probe (counter calibration)")
     ap.add_argument("--serving-only", action="store_true", help="only run the serving comparison")
+    ap.add_argument("--workload", choices=["single", "small", "multi", "pathological"], default="single",
+                    help="single is the benchmark; the others measure the remaining configurations")
+    ap.add_argument("--multi-lines", type=int, default=4_000_000)
     ap.add_argument("--copy-bytes", type=int, default=1 << 28)
     args = ap.parse_args()
 
@@ -73,6 +102,10 @@ def main():
         return
     if args.serving_only:
         print(json.dumps(run_serving(args, torch)), flush=True)
+        return
+    if args.workload != "single":
+        fn = {"small": run_small, "multi": run_multi, "pathological": run_pathological}[args.workload]
+        print(json.dumps(fn(args, torch, dev)), flush=True)
         return
     t0 = time.time()
     prog = W.single_program(1)
@@ -156,6 +189,10 @@ def main():
     if serving:
         log(f"serving: {serving}")
 
+    kid = kernel_id(p, f"layout={args.layout};variant={args.variant};unroll={args.unroll};block={args.block};"
+                       f"grid={args.grid}")
+    traffic = recorded_traffic(kid)
+    log(f"kernel id {kid}; recorded traffic per launch: {traffic}")
     variant_name = {0: "auto", 1: "lane", 2: "wave", 3: "sliced"}[args.variant]
     if args.variant == 0:
         variant_name = "sliced" if (args.layout == "fixed" and not args.no_jit) else "lane"
@@ -183,6 +220,7 @@ def main():
             "kernel": variant_name,
             "input_copies": len(copies),
             "layout": args.layout,
+            "kernel_id": kid,
         },
         "roofline": {
             "bound": "hbm",
@@ -190,13 +228,112 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": None,
+            "traffic": traffic,
         },
         "cpu_baseline": cpu,
         "copy_probe": copy,
         "serving": serving,
     }
     print(json.dumps(rec), flush=True)
+
+
+def run_small(args, torch, dev):
+    """The small configuration: one anchored expression over {a,b}, 1,000 strings; launch-bound."""
+    import oracle
+    from paper_1108_3126_amd import rx
+    from paper_1108_3126_amd import workloads as W
+
+    prog, s = W.small_program(0), W.small_strings(0)
+    p = rx.compile(prog.ast, prog.root, prog.classes, False).upload(dev)
+    d, o = torch.from_numpy(s.data).to(dev), torch.from_numpy(s.offsets).to(dev)
+    out = torch.empty(s.n, dtype=torch.uint8, device=dev)
+    for _ in range(20):
+        rx.match(p, d, o, out=out)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(200)]
+    for a, e in ev:
+        a.record()
+        rx.match(p, d, o, out=out)
+        e.record()
+    torch.cuda.synchronize()
+    us = sorted(a.elapsed_time(e) * 1e3 for a, e in ev)
+    ok = bool(np.array_equal(out.cpu().numpy(), oracle.match(prog.ast, prog.root, prog.classes, False, s.data,
+                                                           s.offsets)))
+    return {"metric": "us per call", "workload": "small: 1 expression over {a,b}, 1,000 strings of length 0..32",
+            "median_us": round(us[len(us) // 2], 2), "p99_us": round(us[int(len(us) * 0.99)], 2), "bit_exact": ok}
+
+
+def run_multi(args, torch, dev):
+    """16 programs against 4M log-normal Zipf lines in one batched launch."""
+    import oracle
+    from paper_1108_3126_amd import autotune, rx
+    from paper_1108_3126_amd import workloads as W
+
+    t0 = time.time()
+    progs = W.multi_programs(seed=2)
+    lines = W.multi_lines(seed=2, n=args.multi_lines)
+    log(f"multi: {len(progs)} programs, {lines.n} lines, {lines.offsets[-1] / 1e6:.0f} MB in {time.time() - t0:.1f}s")
+    ps = [rx.compile(p.ast, p.root, p.classes, True).upload(dev) for p in progs]
+    d, o = torch.from_numpy(lines.data).to(dev), torch.from_numpy(lines.offsets).to(dev)
+    cfg, tinfo = autotune.tune_multi(ps, d, o, budget_runs=40, use_cache=False)
+    log(f"multi tuned: {tinfo}")
+    out = rx.match_multi(ps, d, o, config=cfg)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        rx.match_multi(ps, d, o, out=out, config=cfg)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    got = out.cpu().numpy()
+    rng = np.random.default_rng(7)
+    ok = True
+    for k, pr in enumerate(progs):
+        idx = np.unique(rng.choice(lines.n, size=150, replace=False)).astype(np.int64)
+        want = oracle.match(pr.ast, pr.root, pr.classes, True, lines.data, lines.offsets, index=idx)
+        ok = ok and bool(np.array_equal(got[k][idx], want))
+    nbytes = int(lines.offsets[-1])
+    return {"metric": "unique input GB/s, all programs per line", "workload": "multi: 16 programs x 4M lines",
+            "ms": round(ms, 3), "input_GBs": round(nbytes / (ms * 1e-3) / 1e9, 2),
+            "byte_program_steps_per_s": round(nbytes * len(progs) / (ms * 1e-3), 0),
+            "accepted_per_program": got.sum(axis=1).tolist(), "config": tinfo, "bit_exact_sample": ok}
+
+
+def run_pathological(args, torch, dev):
+    """4,096-node nested-star programs on a^n strings: time per n and linearity ratios."""
+    import oracle
+    from paper_1108_3126_amd import rx
+    from paper_1108_3126_amd import workloads as W
+
+    res = {"metric": "ms per launch (256 strings of length n)", "workload": "pathological", "families": {}}
+    for family, k in (("nested", 819), ("altstar", 585)):
+        prog = W.pathological_program(family, k)
+        p = rx.compile(prog.ast, prog.root).upload(dev)
+        fam = {}
+        for n_len in (1000, 10000, 100000):
+            s = W.pathological_strings(family, n_len, count=256)
+            d = torch.from_numpy(s.data).to(dev)
+            out = rx.match_fixed(p, d, n_len, s.n)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rx.match_fixed(p, d, n_len, s.n, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            closed = bool(got[:128].sum() == 0 and got[128:].all())  # a* t
+            entry = {"ms": round(e0.elapsed_time(e1), 3), "closed_form_ok": closed}
+            if n_len == 1000:
+                idx = np.array([0, 1, 127, 128, 200, 255], np.int64)
+                want = oracle.match(prog.ast, prog.root, prog.classes, False, s.data, s.offsets, index=idx)
+                entry["oracle_ok"] = bool(np.array_equal(got[idx], want))
+            fam[str(n_len)] = entry
+            log(f"pathological {family} n={n_len}: {entry}")
+        fam["ratio_1e4_1e3"] = round(fam["10000"]["ms"] / fam["1000"]["ms"], 2)
+        fam["ratio_1e5_1e4"] = round(fam["100000"]["ms"] / fam["10000"]["ms"], 2)
+        res["families"][family] = fam
+    return res
 
 
 def copy_probe(torch, rx, dev, nbytes, reps=10):

@@ -36,6 +36,7 @@ int make_launch_args(const Program* P, const uint8_t* d_bytes, const int64_t* d_
     a->first = reinterpret_cast<const uint32_t*>(base + P->layout.first);
     a->follow = reinterpret_cast<const uint32_t*>(base + P->layout.follow);
     a->bytemask = reinterpret_cast<const uint32_t*>(base + P->layout.bytemask);
+    a->chunks = P->layout.n_chunks ? reinterpret_cast<const uint32_t*>(base + P->layout.chunks) : nullptr;
     a->L = P->L;
     a->W = P->W;
     a->suffix_any = P->suffix_any ? 1 : 0;

@@ -319,10 +319,34 @@ int compile(const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx_class*
     D.follow = align(D.first + 4 * (int64_t)W);
     D.bytemask = align(D.follow + 4 * (int64_t)L * W);
     D.total = align(D.bytemask + 4 * 256 * (int64_t)W);
+    // Large programs (run one wavefront per string) also get chunk unions:
+    // row (k, v) is the OR of Follow over the leaves 8k + i with bit i set in
+    // v, so a byte step reads one row per non-zero survivor byte instead of
+    // one per survivor.  Built incrementally: T[k][v] = T[k][v & (v-1)] | Follow[8k + ctz v].
+    D.chunks = 0;
+    D.n_chunks = 0;
+    if (W > kLaneMaxWords) {
+        D.n_chunks = 4 * W;  // every byte of every word has a chunk, so no lookup leaves the table
+        D.chunks = D.total;
+        D.total = align(D.chunks + 4 * (int64_t)D.n_chunks * 256 * W);
+    }
     P->blob.assign(D.total, 0);
     std::memcpy(P->blob.data() + D.first, P->first.data(), 4 * (size_t)W);
     if (L) std::memcpy(P->blob.data() + D.follow, P->follow.data(), 4 * (size_t)L * W);
     std::memcpy(P->blob.data() + D.bytemask, P->bytemask.data(), 4 * 256 * (size_t)W);
+    if (D.n_chunks) {
+        uint32_t* T = reinterpret_cast<uint32_t*>(P->blob.data() + D.chunks);
+        for (int32_t k = 0; k < D.n_chunks; ++k) {
+            uint32_t* base = T + (size_t)k * 256 * W;
+            for (int v = 1; v < 256; ++v) {
+                const int i = __builtin_ctz(v);
+                const int32_t r = 8 * k + i;
+                uint32_t* dst = base + (size_t)v * W;
+                const uint32_t* prev = base + (size_t)(v & (v - 1)) * W;
+                for (int w = 0; w < W; ++w) dst[w] = prev[w] | (r < L ? P->follow[(size_t)r * W + w] : 0u);
+            }
+        }
+    }
 
     *out = P;
     return RX_OK;

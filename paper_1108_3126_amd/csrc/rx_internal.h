@@ -23,6 +23,8 @@ struct DevLayout {
     int64_t first = 0;      // words u32
     int64_t follow = 0;     // L * words u32
     int64_t bytemask = 0;   // 256 * words u32
+    int64_t chunks = 0;     // n_chunks * 256 * words u32 (large programs only)
+    int32_t n_chunks = 0;
     int64_t total = 0;
 };
 
@@ -133,6 +135,7 @@ struct LaunchArgs {
     const uint32_t* first;
     const uint32_t* follow;
     const uint32_t* bytemask;
+    const uint32_t* chunks;  // chunk unions, or NULL
     int32_t L, W;
     int32_t suffix_any;
     const uint8_t* bytes;

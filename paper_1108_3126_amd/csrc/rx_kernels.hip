@@ -32,6 +32,7 @@ struct KArgs {
     const uint32_t* first;
     const uint32_t* follow;
     const uint32_t* bytemask;
+    const uint32_t* chunks;
     int32_t L, W, suffix_any, pad;
     const uint8_t* bytes;
     const int64_t* offsets;  // NULL: string i is bytes[i * stride, (i + 1) * stride)
@@ -166,6 +167,17 @@ __global__ __launch_bounds__(1024) void k_wave(KArgs a) {
                         nz &= nz - 1;
                         uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)(half ? X1 : X0), wl);
                         const int wordidx = wl + 64 * half;
+                        if (a.chunks) {
+                            // one union row per survivor byte; the four rows are independent loads
+                            const uint32_t* T = a.chunks + (size_t)wordidx * 4 * 256 * W;
+                            const uint32_t* r0 = T + (size_t)(0 * 256 + ((xw >> 0) & 255u)) * W;
+                            const uint32_t* r1 = T + (size_t)(1 * 256 + ((xw >> 8) & 255u)) * W;
+                            const uint32_t* r2 = T + (size_t)(2 * 256 + ((xw >> 16) & 255u)) * W;
+                            const uint32_t* r3 = T + (size_t)(3 * 256 + ((xw >> 24) & 255u)) * W;
+                            if (own0) N0 |= (r0[lane] | r1[lane]) | (r2[lane] | r3[lane]);
+                            if (own1) N1 |= (r0[lane + 64] | r1[lane + 64]) | (r2[lane + 64] | r3[lane + 64]);
+                            continue;
+                        }
                         while (xw) {
                             const int bit = __builtin_ctz(xw);
                             xw &= xw - 1;
@@ -198,6 +210,7 @@ KArgs kargs(const LaunchArgs& a) {
     k.first = a.first;
     k.follow = a.follow;
     k.bytemask = a.bytemask;
+    k.chunks = a.chunks;
     k.L = a.L;
     k.W = a.W;
     k.suffix_any = a.suffix_any;
