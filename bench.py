@@ -118,7 +118,7 @@ def main():
     if not args.no_jit:
         j0 = time.time()
         p.jit()
-        log(f"bit-sliced circuit compiled in {time.time() - j0:.2f}s: {p.jit_stats()}")
+        log(f"bit-sliced circuit compiled in {time.time() - j0:.2f}s: {p.jit_stats()}, staging {p.jit_staging()}")
     offs = torch.from_numpy(strings.offsets).to(dev)
     copies = [torch.from_numpy(strings.data).to(dev)]
     for _ in range(1, max(1, args.copies)):

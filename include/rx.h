@@ -188,7 +188,13 @@ typedef struct {
     int32_t block;          /* threads per workgroup (multiple of 64, <= 1024) */
     int32_t grid;           /* workgroups (0 = enough for one pass over the strings) */
     int32_t unroll;         /* sliced: 1 = prefetch the next tile into registers while matching,
-                               2 = load each tile, then match it, 3 = a loader wave fetches 64-byte bursts (default) */
+                               2 = load each tile, then match it, 3 = a loader wave fetches 64-byte bursts,
+                               4 = as 3, and the second wave also transposes bytes into bit planes while the
+                               first runs the circuit, 5 = as 4, with each wave fetching whole 64-byte bursts
+                               for half of the strings, that half running 32 bytes behind the other so the two
+                               waves' requests alternate (default).  A program whose staged kernels (1, 3, 4,
+                               5) would spill registers runs 2 instead; 5 needs length <= 2^26 (else 4).
+                               0 = 5 when its kernel was kept, else 3, else 2. */
 } rx_launch;
 
 /* rx_match with an explicit kernel variant and launch shape (the autotuner's
@@ -234,6 +240,15 @@ int rx_program_jit_source(const rx_program* prog, char* buf, size_t cap, size_t*
  * live thread state per lane; ops: bitwise operations per byte step before
  * the device compiler's own simplification. */
 int rx_program_jit_stats(const rx_program* prog, int32_t* ready, int32_t* state_words, int32_t* ops);
+
+/* Which staging modes of the sliced kernel (rx_launch.unroll) run as
+ * themselves for this program: staged[u] = 1 for mode u in 1..5 when its
+ * kernel was kept, 0 when it was dropped (the device compiler spilled its
+ * registers) and mode 2 runs in its place; staged[2] = 1 whenever the program
+ * is compiled; staged[0] = the mode that unroll = 0 selects.  All zero before
+ * rx_program_jit, or where the program has no loaded kernel.
+ * Errors: RX_EINVAL (NULL arguments). */
+int rx_program_jit_staging(const rx_program* prog, int32_t staged[6]);
 
 /* Length bucketing and launch shape of rx_match_multi; zero fields mean default. */
 typedef struct {

@@ -232,10 +232,10 @@ int rx_match_fixed_ex(const rx_program* prog, const uint8_t* d_bytes, int64_t le
         {
             int dev = -1;
             hip_current_device(&dev);
-            if (a.unroll < 0 || a.unroll > 3)
-                return fail(RX_EINVAL, "sliced kernel staging (unroll) must be 1 (prefetch), 2 (load then match) "
-                                       "or 3 (loader wave)");
-            e = launch_sliced_fixed(P, d_bytes, length, n, d_out, a.unroll ? a.unroll : 3, stream);
+            if (a.unroll < 0 || a.unroll > 5)
+                return fail(RX_EINVAL, "sliced kernel staging (unroll) must be 1 (prefetch), 2 (load then match), "
+                                       "3 (loader wave), 4 (transposing wave) or 5 (skewed sets)");
+            e = launch_sliced_fixed(P, d_bytes, length, n, d_out, a.unroll ? a.unroll : jit_default_staging(P), stream);
         }
         break;
     case RX_VARIANT_LANE:
@@ -402,6 +402,12 @@ int rx_program_jit_stats(const rx_program* prog, int32_t* ready, int32_t* state_
     if (ready) *ready = r ? 1 : 0;
     if (state_words) *state_words = ns;
     if (ops) *ops = no;
+    return RX_OK;
+}
+
+int rx_program_jit_staging(const rx_program* prog, int32_t staged[6]) {
+    if (!prog || !staged) return fail(RX_EINVAL, "NULL argument");
+    jit_staging(reinterpret_cast<const Program*>(prog), staged);
     return RX_OK;
 }
 

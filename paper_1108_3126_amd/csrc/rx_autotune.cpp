@@ -113,7 +113,7 @@ int autotune_single(const Program* P, const uint8_t* d_bytes, const int64_t* d_o
     const bool fixed = d_offsets == nullptr;
     if (fixed && jit_ready(P, nullptr, nullptr) && length > 0 && length % 16 == 0 &&
         (reinterpret_cast<uintptr_t>(d_bytes) & 15) == 0)
-        for (int burst : {1, 2, 3}) {
+        for (int burst : {1, 2, 3, 4, 5}) {
             add(RX_VARIANT_SLICED, 0, 0);
             cands.back().launch.unroll = burst;
         }

@@ -153,6 +153,10 @@ std::string jit_full_source(const Program& P, int* n_state, int* n_ops);
 int jit_compile(Program* P, const char* arch);
 void jit_free(Program* P);
 bool jit_ready(const Program* P, int* n_state, int* n_ops);
+// staged[u] for staging modes u = 0..5 (see rx_program_jit_staging).
+void jit_staging(const Program* P, int32_t staged[6]);
+// The staging mode that unroll = 0 selects.
+int jit_default_staging(const Program* P);
 int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,
                         int burst, void* stream);
 int launch_wave(const LaunchArgs& a);

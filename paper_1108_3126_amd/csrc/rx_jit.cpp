@@ -458,6 +458,212 @@ extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_duo(const u
     if (wave == 0) rx_store_result(out, base, n, lane, acc);
 }
 
+// Transposer and circuit on two SIMDs.  Data move as in the two-wave kernel
+// (64-byte bursts split between the waves' registers, written to the LDS tile
+// in halves), but the second wave also turns the tile into bit planes, four
+// positions at a time, into a two-slot ring; the first wave runs the circuit
+// one slot behind.  Slot layout: 8 quads of plane words per lane, quad-major,
+// so both sides move 16 bytes per lane per access without bank conflicts.
+#define RX_SLOT_WORDS (32 * 64)
+__device__ __forceinline__ void rx_tile_to_planes(const u32* rx_tile, u32* slot, int lane, int grp) {
+    u32 w[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) w[j] = rx_tile[(j * 64 + lane) * 8 + grp];
+    rx_transpose32(w);
+    rx_v4* d = reinterpret_cast<rx_v4*>(slot);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        rx_v4 v;
+        v.x = w[4 * k];
+        v.y = w[4 * k + 1];
+        v.z = w[4 * k + 2];
+        v.w = w[4 * k + 3];
+        d[k * 64 + lane] = v;
+    }
+}
+
+__device__ __forceinline__ void rx_run_planes(const u32* slot, int lane, u32 (&s)[RX_NS], u32& acc) {
+    const rx_v4* q = reinterpret_cast<const rx_v4*>(slot);
+    u32 w[32];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const rx_v4 v = q[k * 64 + lane];
+        w[4 * k] = v.x;
+        w[4 * k + 1] = v.y;
+        w[4 * k + 2] = v.z;
+        w[4 * k + 3] = v.w;
+    }
+    rx_step(s, acc, w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7]);
+    rx_step(s, acc, w[8], w[9], w[10], w[11], w[12], w[13], w[14], w[15]);
+    rx_step(s, acc, w[16], w[17], w[18], w[19], w[20], w[21], w[22], w[23]);
+    rx_step(s, acc, w[24], w[25], w[26], w[27], w[28], w[29], w[30], w[31]);
+}
+
+// length must be a multiple of 16 (whole 4-position groups, whole 16-byte loads).
+extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_split(const unsigned char* __restrict__ bytes,
+        long long length, long long n, unsigned char* __restrict__ out) {
+    extern __shared__ u32 rx_tile[];                   // 32-byte tile of every string, then the ring
+    u32* rx_ring = rx_tile + RX_WAVE_STRINGS * 8;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const long long base = (long long)blockIdx.x * RX_WAVE_STRINGS;
+    u32 s[RX_NS];
+    u32 acc;
+    rx_init(s, acc);
+    const long long nbursts = (length + 63) / 64;
+    const long long ngroups = length / 4;
+    rx_v4 nx[RX_WAVE_STRINGS / 32];
+    rx_issue_half(bytes, length, n, base, lane, wave * 32, nx);
+    // tick g: wave 1 transposes group g, wave 0 runs group g - 1
+    for (long long g = 0; g <= ngroups; ++g) {
+        if ((g & 7) == 0 && g < ngroups) {
+            // group g opens half h of the string; the tile's previous half was
+            // last read by wave 1 in the tick before
+            const long long h = g >> 3;
+            const long long k = h >> 1;
+            const int half = (int)(h & 1);
+            if (wave == half) rx_regs_to_tile(rx_tile, lane, nx);
+            __syncthreads();
+            if (half == 1 && k + 1 < nbursts) rx_issue_half(bytes, length, n, base, lane, (k + 1) * 64 + wave * 32, nx);
+        }
+        if (wave == 1) {
+            if (g < ngroups) rx_tile_to_planes(rx_tile, rx_ring + (int)(g & 1) * RX_SLOT_WORDS, lane, (int)(g & 7));
+        } else if (g > 0) {
+            rx_run_planes(rx_ring + (int)((g - 1) & 1) * RX_SLOT_WORDS, lane, s, acc);
+        }
+        __syncthreads();
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // a trailing half that was never matched has landed
+    if (wave == 0) rx_store_result(out, base, n, lane, acc);
+}
+
+// Skewed sets.  The 2048 strings of a workgroup form two sets: bits 0-15 of
+// every word (strings 0-1023) and bits 16-31 (strings 1024-2047).  The circuit
+// wave fetches the first set's 64-byte bursts, the transposing wave the
+// second's, and the second set runs one 32-byte half behind the first.  A
+// wave requests its set's next burst as soon as the previous one has moved to
+// the tile, so the two sets' requests alternate from half to half and one is
+// always in flight while the circuit runs.  The second set's bits take
+// garbage during the first half and are reset to the start state before its
+// first byte; the first set's accept bits are taken after its last byte.
+#define RX_SET_STRINGS 1024
+// Burst (off / 64) of every string of one set: instruction q takes 16 bytes of
+// string q * 32 + lane / 2 into nx[q] (first 32 bytes of the burst) and into
+// nx[q + 32] (second 32), back to back.  Addresses are a uniform base (scalar
+// registers) plus a 32-bit per-lane offset, formed at the load, so no address
+// stays live across the loop.  off < length and length % 16 == 0.
+__device__ __forceinline__ void rx_gload(rx_v4& dst, const unsigned char* sp, u32 voff) {
+    asm volatile("global_load_dwordx4 %0, %1, %2" : "=a"(dst) : "v"(voff), "s"(sp) : "memory");
+}
+// B = 0: every instruction but the last (nx[63]); B = 1: only that one;
+// B < 0: all of them.
+template <int B>
+__device__ __forceinline__ void rx_issue_set(const unsigned char* __restrict__ bytes, long long length, long long n,
+                                             long long sbase, int lane, long long off, rx_v4 (&nx)[64]) {
+    const long long room = length - 16 - off;   // >= 0; past a string's end: an in-bounds duplicate, never matched
+    const long long da = 16 * (lane & 1) < room ? 16 * (lane & 1) : room;
+    const long long db = 32 + 16 * (lane & 1) < room ? 32 + 16 * (lane & 1) : room;
+    if (sbase + RX_SET_STRINGS <= n) {
+        const u32 va = (u32)((lane >> 1) * length + da), vb = (u32)((lane >> 1) * length + db);
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            const unsigned char* sp = bytes + (sbase + q * 32) * length + off;
+            if (B != 1) rx_gload(nx[q], sp, va);
+            if (B < 0 || (B == 0 && q < 31) || (B == 1 && q == 31)) rx_gload(nx[q + 32], sp, vb);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            long long bq = sbase + q * 32;
+            if (bq > n - 1) bq = n - 1;
+            long long r = lane >> 1;
+            if (r > n - 1 - bq) r = n - 1 - bq;
+            const unsigned char* sp = bytes + bq * length + off;
+            if (B != 1) rx_gload(nx[q], sp, (u32)(r * length + da));
+            if (B < 0 || (B == 0 && q < 31) || (B == 1 && q == 31)) rx_gload(nx[q + 32], sp, (u32)(r * length + db));
+        }
+    }
+}
+
+// Moves one half of the set's burst (SECOND = its last 32 bytes) to the set's tile.
+template <int SECOND>
+__device__ __forceinline__ void rx_set_to_tile(u32* tile_set, int lane, rx_v4 (&nx)[64]) {
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+        const u32 a = (u32)(unsigned long long)(rx_lds_u32*)(tile_set + q * 256 + 4 * lane);
+        asm volatile("ds_write_b128 %0, %1" ::"v"(a), "a"(nx[q + 32 * SECOND]) : "memory");
+    }
+    // the writes have read their registers before any load refills them
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// length must be a multiple of 16.
+extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_skew(const unsigned char* __restrict__ bytes,
+        long long length, long long n, unsigned char* __restrict__ out) {
+    extern __shared__ u32 rx_tile[];                   // 32-byte tile of every string, then the ring
+    u32* rx_ring = rx_tile + RX_WAVE_STRINGS * 8;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const long long base = (long long)blockIdx.x * RX_WAVE_STRINGS;
+    const long long sbase = base + (long long)wave * RX_SET_STRINGS;
+    u32* tile_set = rx_tile + wave * RX_SET_STRINGS * 8;
+    const long long nbursts = (length + 63) / 64;
+    const long long nhalves = (length + 31) / 32;
+    const long long ngroups = length / 4;
+    const long long nticks = ngroups + 8;   // the second set's groups come 8 ticks late
+    u32 s[RX_NS];
+    u32 acc;
+    rx_init(s, acc);
+    u32 acc_first = 0;
+    rx_v4 nx[64];
+    rx_issue_set<-1>(bytes, length, n, sbase, lane, 0, nx);
+    // tick T: the transposing wave makes plane group T (first set: group T of
+    // its string, second set: group T - 8), the circuit wave runs group T - 1
+    long long hh = 0;   // the half this wave's set is in
+    for (long long T = 0; T <= nticks; ++T) {
+        if ((T & 7) == 0 && T < nticks) {
+            hh = (T >> 3) - wave;
+            if (hh >= 0 && hh < nhalves) {
+                if ((hh & 1) == 0) {
+                    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                    rx_set_to_tile<0>(tile_set, lane, nx);
+                } else {
+                    // the burst landed with its first half
+                    rx_set_to_tile<1>(tile_set, lane, nx);
+                }
+            }
+            // The registers are free once the burst's second half is in the
+            // tile.  A wave holds at most 63 loads in flight (a 64th would
+            // stall it until the first returns), so the last load of the
+            // burst waits two ticks.
+            if (hh >= 0 && hh < nhalves && (hh & 1) == 1 && (hh >> 1) + 1 < nbursts)
+                rx_issue_set<0>(bytes, length, n, sbase, lane, ((hh >> 1) + 1) * 64, nx);
+            __syncthreads();
+        }
+        if ((T & 7) == 2 && T < nticks && hh >= 0 && hh < nhalves && (hh & 1) == 1 && (hh >> 1) + 1 < nbursts)
+            rx_issue_set<1>(bytes, length, n, sbase, lane, ((hh >> 1) + 1) * 64, nx);
+        if (wave == 1) {
+            if (T < nticks) rx_tile_to_planes(rx_tile, rx_ring + (int)(T & 1) * RX_SLOT_WORDS, lane, (int)(T & 7));
+        } else if (T > 0) {
+            const long long P = T - 1;
+            if (P == 8) {
+                // the second set's first byte: its bits restart from the start state
+                u32 s0[RX_NS];
+                u32 a0;
+                rx_init(s0, a0);
+#pragma unroll
+                for (int i = 0; i < RX_NS; ++i) s[i] = (s[i] & 0x0000ffffu) | (s0[i] & 0xffff0000u);
+                acc = (acc & 0x0000ffffu) | (a0 & 0xffff0000u);
+            }
+            rx_run_planes(rx_ring + (int)(P & 1) * RX_SLOT_WORDS, lane, s, acc);
+            if (P == ngroups - 1) acc_first = acc;
+        }
+        __syncthreads();
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // loads past the last matched half have landed
+    if (wave == 0) rx_store_result(out, base, n, lane, (acc_first & 0x0000ffffu) | (acc & 0xffff0000u));
+}
+
 extern "C" __global__ __launch_bounds__(64, 1) void rx_sliced_fixed_pf(const unsigned char* __restrict__ bytes,
         long long length, long long n, unsigned char* __restrict__ out) {
     extern __shared__ u32 rx_tile[];
@@ -492,6 +698,8 @@ struct JitKernel {
     hipFunction_t fixed = nullptr;
     hipFunction_t fixed64 = nullptr;
     hipFunction_t duo = nullptr;
+    hipFunction_t split = nullptr;
+    hipFunction_t skew = nullptr;
     int dev = -1;
     int n_state = 0, n_ops = 0;
     std::string arch;
@@ -526,8 +734,8 @@ int jit_compile(Program* P, const char* arch_in) {
     if (hiprtcCreateProgram(&prog, src.c_str(), "rx_sliced.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
         return fail(RX_EJIT, "hiprtcCreateProgram failed");
     const std::string arch_opt = "--gpu-architecture=" + arch;
-    const char* opts[] = {arch_opt.c_str(), "-O3", "-std=c++17"};
-    const hiprtcResult rc = hiprtcCompileProgram(prog, 3, opts);
+    const char* opts[] = {arch_opt.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    const hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
     if (rc != HIPRTC_SUCCESS) {
         size_t n = 0;
         hiprtcGetProgramLogSize(prog, &n);
@@ -551,10 +759,21 @@ int jit_compile(Program* P, const char* arch_in) {
         e = hipModuleGetFunction(&K->fixed, K->mod, "rx_sliced_fixed");
         if (e == hipSuccess) e = hipModuleGetFunction(&K->fixed64, K->mod, "rx_sliced_fixed_pf");
         if (e == hipSuccess) e = hipModuleGetFunction(&K->duo, K->mod, "rx_sliced_fixed_duo");
+        if (e == hipSuccess) e = hipModuleGetFunction(&K->split, K->mod, "rx_sliced_fixed_split");
+        if (e == hipSuccess) e = hipModuleGetFunction(&K->skew, K->mod, "rx_sliced_fixed_skew");
         if (e != hipSuccess) {
             hipModuleUnload(K->mod);
             delete K;
             return fail(RX_EHIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));
+        }
+        // The staged kernels keep in-flight loads in registers the compiler
+        // believes already hold their data; a kernel that spills could move
+        // such a register before its load lands.  Those kernels are dropped
+        // for this program and the LDS-staged kernel runs instead.
+        for (hipFunction_t* f : {&K->fixed64, &K->duo, &K->split, &K->skew}) {
+            int scratch = 1;
+            if (hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, *f) != hipSuccess || scratch != 0)
+                *f = nullptr;
         }
         K->dev = dev;
     }
@@ -578,14 +797,39 @@ bool jit_ready(const Program* P, int* n_state, int* n_ops) {
     return K && K->fixed;
 }
 
+int jit_default_staging(const Program* P) {
+    const JitKernel* K = static_cast<const JitKernel*>(P->jit);
+    if (!K || !K->fixed) return 0;
+    return K->skew ? 5 : K->duo ? 3 : 2;
+}
+
+void jit_staging(const Program* P, int32_t staged[6]) {
+    for (int u = 0; u < 6; ++u) staged[u] = 0;
+    const JitKernel* K = static_cast<const JitKernel*>(P->jit);
+    if (!K || !K->fixed) return;
+    staged[0] = jit_default_staging(P);
+    staged[1] = K->fixed64 ? 1 : 0;
+    staged[2] = 1;
+    staged[3] = K->duo ? 1 : 0;
+    staged[4] = K->split ? 1 : 0;
+    staged[5] = K->skew ? 1 : 0;
+}
+
 int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,
                         int burst, void* stream) {
     const JitKernel* K = static_cast<const JitKernel*>(P->jit);
-    if (!K || !K->fixed || !K->fixed64 || !K->duo) return (int)hipErrorInvalidValue;
-    hipFunction_t fn = burst == 1 ? K->fixed64 : burst == 3 ? K->duo : K->fixed;
-    const unsigned threads = burst == 3 ? 128 : 64;
+    if (!K || !K->fixed) return (int)hipErrorInvalidValue;
+    if (burst == 5 && length > (1 << 26)) burst = 4;   // the skewed kernel forms 32-bit per-lane offsets
+    hipFunction_t fn = burst == 1 ? K->fixed64 : burst == 3 ? K->duo : burst == 4 ? K->split : burst == 5 ? K->skew
+                                                                                                          : K->fixed;
+    if (!fn) {   // dropped for this program
+        fn = K->fixed;
+        burst = 2;
+    }
+    const unsigned threads = burst >= 3 ? 128 : 64;
     const long long grid = (n + 2047) / 2048;
-    const unsigned lds = 2048 * 32;
+    // raw tile: 2048 strings x 32 bytes; the transposing kernels add two 8 KiB plane slots
+    const unsigned lds = 2048 * 32 + (burst >= 4 ? 2 * 2048 * 4 : 0);
     long long len = length, nn = n;
     const void* b = bytes;
     void* o = out;

@@ -97,6 +97,7 @@ SIGNATURES = {
     "rx_program_jit": (ctypes.c_int, [_VP, ctypes.c_char_p]),
     "rx_program_jit_source": (ctypes.c_int, [_VP, ctypes.c_char_p, _SZ, ctypes.POINTER(_SZ)]),
     "rx_program_jit_stats": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "rx_program_jit_staging": (ctypes.c_int, [_VP, ctypes.POINTER(_I32)]),
     "rx_match_multi_workspace": (ctypes.c_int64, [_I64, _I32, ctypes.POINTER(rx_multi_config)]),
     "rx_match_multi": (ctypes.c_int, [ctypes.POINTER(_VP), _I32, _VP, _VP, _I64, _VP, _VP, _SZ,
                                       ctypes.POINTER(rx_multi_config), _VP]),
@@ -232,6 +233,12 @@ class Program:
         r, s, o = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib().rx_program_jit_stats(self._h, ctypes.byref(r), ctypes.byref(s), ctypes.byref(o)))
         return {"ready": r.value, "state_words": s.value, "ops": o.value}
+
+    def jit_staging(self):
+        """[default mode, then 1/0 for staging modes 1..5]: which sliced kernels run as themselves."""
+        st = (ctypes.c_int32 * 6)()
+        _check(lib().rx_program_jit_staging(self._h, st))
+        return list(st)
 
     # -- device -----------------------------------------------------------
     def upload(self, device=None, stream=None):

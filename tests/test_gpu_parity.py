@@ -181,15 +181,20 @@ def test_sliced_single_program(dev):
     s, planted = W.single_strings(prog, seed=21, n=5000, length=256)
     p = rx.compile(prog.ast, prog.root, prog.classes, True).upload(dev).jit()
     assert p.jit_stats()["ready"] == 1
+    staging = p.jit_staging()
+    print("sliced single: staging", staging, flush=True)
+    assert staging[0] == 5 and staging[5] == 1   # the skewed kernel is kept and is the default
     want = oracle_match(prog, s)
     print("sliced single: accepted", int(want.sum()), flush=True)
     for v in (rx.VARIANT_SLICED, rx.VARIANT_LANE, rx.VARIANT_WAVE, 0):
         assert np.array_equal(fixed_match(p, s, 256, dev, v), want), v
     assert np.array_equal(fixed_match(p, s, 256, dev, rx.VARIANT_SLICED, 2), want)
     assert np.array_equal(fixed_match(p, s, 256, dev, rx.VARIANT_SLICED, 3), want)
+    assert np.array_equal(fixed_match(p, s, 256, dev, rx.VARIANT_SLICED, 4), want)
+    assert np.array_equal(fixed_match(p, s, 256, dev, rx.VARIANT_SLICED, 5), want)
 
 
-@pytest.mark.parametrize("burst", [1, 2, 3])
+@pytest.mark.parametrize("burst", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("length", [16, 32, 48, 64, 80, 112, 272])
 def test_sliced_lengths_and_counts(dev, length, burst):
     from paper_1108_3126_amd import rx
@@ -216,7 +221,8 @@ def test_sliced_small_programs(dev, seed):
             s = W.Strings(data, np.arange(3001, dtype=np.int64) * 32)
             prog.search = search
             want = oracle_match(prog, s)
-            assert np.array_equal(fixed_match(p, s, 32, dev, rx.VARIANT_SLICED), want), (seed, k, search)
+            for burst in (3, 4, 5):
+                assert np.array_equal(fixed_match(p, s, 32, dev, rx.VARIANT_SLICED, burst), want), (seed, k, search)
 
 
 def test_sliced_pathological(dev):
@@ -228,7 +234,8 @@ def test_sliced_pathological(dev):
         p = rx.compile(prog.ast, prog.root).upload(dev).jit()
         want = oracle_match(prog, s)
         assert want[:32].sum() == 0 and want[32:].all()
-        assert np.array_equal(fixed_match(p, s, 1008, dev, rx.VARIANT_SLICED), want), family
+        for burst in (3, 4, 5):
+            assert np.array_equal(fixed_match(p, s, 1008, dev, rx.VARIANT_SLICED, burst), want), family
     big = W.pathological_program("altstar", 585)
     with pytest.raises(rx.RxError) as ei:
         rx.compile(big.ast, big.root).jit()

@@ -142,3 +142,5 @@ def test_hiprtc_compiles_for_gfx950():
     p.jit("gfx950")  # no device needed to compile
     st = p.jit_stats()
     assert st["ready"] == 0 and st["state_words"] > 0 and st["ops"] > 0
+    # nothing is loaded without a device: no staging mode is available yet
+    assert p.jit_staging() == [0, 0, 0, 0, 0, 0]
