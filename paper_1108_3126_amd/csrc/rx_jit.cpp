@@ -547,9 +547,9 @@ extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_split(const
 // garbage during the first half and are reset to the start state before its
 // first byte; the first set's accept bits are taken after its last byte.
 #define RX_SET_STRINGS 1024
-// Burst (off / 64) of every string of one set: instruction q takes 16 bytes of
-// string q * 32 + lane / 2 into nx[q] (first 32 bytes of the burst) and into
-// nx[q + 32] (second 32), back to back.  Addresses are a uniform base (scalar
+// Burst (off / 64) of every string of one set: instruction q takes 16 bytes
+// (chunk lane / 32) of string q * 32 + lane % 32 into nx[q] (first 32 bytes of
+// the burst) and into nx[q + 32] (second 32), back to back.  Addresses are a uniform base (scalar
 // registers) plus a 32-bit per-lane offset, formed at the load, so no address
 // stays live across the loop.  off < length and length % 16 == 0.
 __device__ __forceinline__ void rx_gload(rx_v4& dst, const unsigned char* sp, u32 voff) {
@@ -561,10 +561,11 @@ template <int B>
 __device__ __forceinline__ void rx_issue_set(const unsigned char* __restrict__ bytes, long long length, long long n,
                                              long long sbase, int lane, long long off, rx_v4 (&nx)[64]) {
     const long long room = length - 16 - off;   // >= 0; past a string's end: an in-bounds duplicate, never matched
-    const long long da = 16 * (lane & 1) < room ? 16 * (lane & 1) : room;
-    const long long db = 32 + 16 * (lane & 1) < room ? 32 + 16 * (lane & 1) : room;
+    const int c = lane >> 5;
+    const long long da = 16 * c < room ? 16 * c : room;
+    const long long db = 32 + 16 * c < room ? 32 + 16 * c : room;
     if (sbase + RX_SET_STRINGS <= n) {
-        const u32 va = (u32)((lane >> 1) * length + da), vb = (u32)((lane >> 1) * length + db);
+        const u32 va = (u32)((lane & 31) * length + da), vb = (u32)((lane & 31) * length + db);
 #pragma unroll
         for (int q = 0; q < 32; ++q) {
             const unsigned char* sp = bytes + (sbase + q * 32) * length + off;
@@ -576,7 +577,7 @@ __device__ __forceinline__ void rx_issue_set(const unsigned char* __restrict__ b
         for (int q = 0; q < 32; ++q) {
             long long bq = sbase + q * 32;
             if (bq > n - 1) bq = n - 1;
-            long long r = lane >> 1;
+            long long r = lane & 31;
             if (r > n - 1 - bq) r = n - 1 - bq;
             const unsigned char* sp = bytes + bq * length + off;
             if (B != 1) rx_gload(nx[q], sp, (u32)(r * length + da));
@@ -585,28 +586,80 @@ __device__ __forceinline__ void rx_issue_set(const unsigned char* __restrict__ b
     }
 }
 
-// Moves one half of the set's burst (SECOND = its last 32 bytes) to the set's tile.
+// Moves one half of the set's burst (SECOND = its last 32 bytes) to the tile,
+// which holds the current 32 bytes of every string as two 16-byte chunks,
+// chunk-major: chunk c of string s (0 .. 2047) at 16-byte slot c * 2048 + s.
+// Consecutive lanes write consecutive slots, and the transposing wave reads
+// one dword of 64 consecutive slots at a time.
 template <int SECOND>
-__device__ __forceinline__ void rx_set_to_tile(u32* tile_set, int lane, rx_v4 (&nx)[64]) {
+__device__ __forceinline__ void rx_set_to_tile(u32* rx_tile, int set_off, int lane, rx_v4 (&nx)[64]) {
 #pragma unroll
     for (int q = 0; q < 32; ++q) {
-        const u32 a = (u32)(unsigned long long)(rx_lds_u32*)(tile_set + q * 256 + 4 * lane);
+        const int slot = (lane >> 5) * RX_WAVE_STRINGS + set_off + q * 32 + (lane & 31);
+        const u32 a = (u32)(unsigned long long)(rx_lds_u32*)(rx_tile + slot * 4);
         asm volatile("ds_write_b128 %0, %1" ::"v"(a), "a"(nx[q + 32 * SECOND]) : "memory");
     }
     // the writes have read their registers before any load refills them
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
-// length must be a multiple of 16.
-extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_skew(const unsigned char* __restrict__ bytes,
-        long long length, long long n, unsigned char* __restrict__ out) {
-    extern __shared__ u32 rx_tile[];                   // 32-byte tile of every string, then the ring
+// Plane groups of the chunk-major tile.  At an even group g the transposing
+// lane reads dwords g % 4 and g % 4 + 1 of chunk g / 4 of its 32 strings
+// (string j * 64 + lane) as one 8-byte access each and makes group g from the
+// first; group g + 1 comes from the second, already in registers.
+typedef unsigned int rx_v2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void rx_read_pairs(const u32* rx_tile, int g, int lane, rx_v2 (&raw)[32]) {
+    const rx_v2* t = reinterpret_cast<const rx_v2*>(rx_tile) + (g >> 2) * (RX_WAVE_STRINGS * 2) + ((g & 3) >> 1);
+#pragma unroll
+    for (int j = 0; j < 32; ++j) raw[j] = t[(j * 64 + lane) * 2];
+}
+// Plane group g read one dword per string (the variant for programs whose
+// circuit leaves no room for the pair registers).
+__device__ __forceinline__ void rx_words_to_planes(const u32* rx_tile, u32* slot, int lane, int g) {
+    u32 w[32];
+    const u32* t = rx_tile + (g >> 2) * (RX_WAVE_STRINGS * 4) + (g & 3);
+#pragma unroll
+    for (int j = 0; j < 32; ++j) w[j] = t[(j * 64 + lane) * 4];
+    rx_transpose32(w);
+    rx_v4* d = reinterpret_cast<rx_v4*>(slot);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        rx_v4 v;
+        v.x = w[4 * k];
+        v.y = w[4 * k + 1];
+        v.z = w[4 * k + 2];
+        v.w = w[4 * k + 3];
+        d[k * 64 + lane] = v;
+    }
+}
+template <int E>
+__device__ __forceinline__ void rx_pairs_to_planes(const rx_v2 (&raw)[32], u32* slot, int lane) {
+    u32 w[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) w[j] = E == 0 ? raw[j].x : raw[j].y;
+    rx_transpose32(w);
+    rx_v4* d = reinterpret_cast<rx_v4*>(slot);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        rx_v4 v;
+        v.x = w[4 * k];
+        v.y = w[4 * k + 1];
+        v.z = w[4 * k + 2];
+        v.w = w[4 * k + 3];
+        d[k * 64 + lane] = v;
+    }
+}
+
+// length must be a multiple of 16.  PAIRS: the transposing wave reads dword
+// pairs (fewer LDS accesses, 64 more registers) rather than single dwords.
+template <bool PAIRS>
+__device__ __forceinline__ void rx_skew(const unsigned char* __restrict__ bytes, long long length, long long n,
+                                        unsigned char* __restrict__ out, u32* rx_tile) {
     u32* rx_ring = rx_tile + RX_WAVE_STRINGS * 8;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const long long base = (long long)blockIdx.x * RX_WAVE_STRINGS;
     const long long sbase = base + (long long)wave * RX_SET_STRINGS;
-    u32* tile_set = rx_tile + wave * RX_SET_STRINGS * 8;
     const long long nbursts = (length + 63) / 64;
     const long long nhalves = (length + 31) / 32;
     const long long ngroups = length / 4;
@@ -619,6 +672,7 @@ extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_skew(const 
     rx_issue_set<-1>(bytes, length, n, sbase, lane, 0, nx);
     // tick T: the transposing wave makes plane group T (first set: group T of
     // its string, second set: group T - 8), the circuit wave runs group T - 1
+    rx_v2 raw[32];
     long long hh = 0;   // the half this wave's set is in
     for (long long T = 0; T <= nticks; ++T) {
         if ((T & 7) == 0 && T < nticks) {
@@ -626,10 +680,10 @@ extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_skew(const 
             if (hh >= 0 && hh < nhalves) {
                 if ((hh & 1) == 0) {
                     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-                    rx_set_to_tile<0>(tile_set, lane, nx);
+                    rx_set_to_tile<0>(rx_tile, wave * RX_SET_STRINGS, lane, nx);
                 } else {
                     // the burst landed with its first half
-                    rx_set_to_tile<1>(tile_set, lane, nx);
+                    rx_set_to_tile<1>(rx_tile, wave * RX_SET_STRINGS, lane, nx);
                 }
             }
             // The registers are free once the burst's second half is in the
@@ -643,7 +697,16 @@ extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_skew(const 
         if ((T & 7) == 2 && T < nticks && hh >= 0 && hh < nhalves && (hh & 1) == 1 && (hh >> 1) + 1 < nbursts)
             rx_issue_set<1>(bytes, length, n, sbase, lane, ((hh >> 1) + 1) * 64, nx);
         if (wave == 1) {
-            if (T < nticks) rx_tile_to_planes(rx_tile, rx_ring + (int)(T & 1) * RX_SLOT_WORDS, lane, (int)(T & 7));
+            if (T < nticks) {
+                if (!PAIRS) {
+                    rx_words_to_planes(rx_tile, rx_ring + (int)(T & 1) * RX_SLOT_WORDS, lane, (int)(T & 7));
+                } else if ((T & 1) == 0) {
+                    rx_read_pairs(rx_tile, (int)(T & 7), lane, raw);
+                    rx_pairs_to_planes<0>(raw, rx_ring + (int)(T & 1) * RX_SLOT_WORDS, lane);
+                } else {
+                    rx_pairs_to_planes<1>(raw, rx_ring + (int)(T & 1) * RX_SLOT_WORDS, lane);
+                }
+            }
         } else if (T > 0) {
             const long long P = T - 1;
             if (P == 8) {
@@ -662,6 +725,18 @@ extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_skew(const 
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // loads past the last matched half have landed
     if (wave == 0) rx_store_result(out, base, n, lane, (acc_first & 0x0000ffffu) | (acc & 0xffff0000u));
+}
+
+extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_skew(const unsigned char* __restrict__ bytes,
+        long long length, long long n, unsigned char* __restrict__ out) {
+    extern __shared__ u32 rx_tile[];   // 32-byte tile of every string, then the ring
+    rx_skew<true>(bytes, length, n, out, rx_tile);
+}
+
+extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_skew_w(const unsigned char* __restrict__ bytes,
+        long long length, long long n, unsigned char* __restrict__ out) {
+    extern __shared__ u32 rx_tile[];
+    rx_skew<false>(bytes, length, n, out, rx_tile);
 }
 
 extern "C" __global__ __launch_bounds__(64, 1) void rx_sliced_fixed_pf(const unsigned char* __restrict__ bytes,
@@ -760,7 +835,9 @@ int jit_compile(Program* P, const char* arch_in) {
         if (e == hipSuccess) e = hipModuleGetFunction(&K->fixed64, K->mod, "rx_sliced_fixed_pf");
         if (e == hipSuccess) e = hipModuleGetFunction(&K->duo, K->mod, "rx_sliced_fixed_duo");
         if (e == hipSuccess) e = hipModuleGetFunction(&K->split, K->mod, "rx_sliced_fixed_split");
+        hipFunction_t skew_w = nullptr;
         if (e == hipSuccess) e = hipModuleGetFunction(&K->skew, K->mod, "rx_sliced_fixed_skew");
+        if (e == hipSuccess) e = hipModuleGetFunction(&skew_w, K->mod, "rx_sliced_fixed_skew_w");
         if (e != hipSuccess) {
             hipModuleUnload(K->mod);
             delete K;
@@ -770,11 +847,12 @@ int jit_compile(Program* P, const char* arch_in) {
         // believes already hold their data; a kernel that spills could move
         // such a register before its load lands.  Those kernels are dropped
         // for this program and the LDS-staged kernel runs instead.
-        for (hipFunction_t* f : {&K->fixed64, &K->duo, &K->split, &K->skew}) {
+        for (hipFunction_t* f : {&K->fixed64, &K->duo, &K->split, &K->skew, &skew_w}) {
             int scratch = 1;
             if (hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, *f) != hipSuccess || scratch != 0)
                 *f = nullptr;
         }
+        if (!K->skew) K->skew = skew_w;   // the skewed kernel with single-dword transposer reads
         K->dev = dev;
     }
     if (P->jit) jit_free(P);

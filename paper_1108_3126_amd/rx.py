@@ -128,6 +128,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_1108_3126_amd.build")
+        # torch brings its own HIP runtime and hiprtc; loading it first makes the
+        # library bind to those, so the process holds one HIP runtime whose
+        # device pointers and streams both sides share
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
