@@ -246,7 +246,9 @@ int rx_program_jit_stats(const rx_program* prog, int32_t* ready, int32_t* state_
  * kernel was kept, 0 when it was dropped (the device compiler spilled its
  * registers) and mode 2 runs in its place; staged[2] = 1 whenever the program
  * is compiled; staged[0] = the mode that unroll = 0 selects.  All zero before
- * rx_program_jit, or where the program has no loaded kernel.
+ * rx_program_jit, or where the program has no loaded kernel.  staged[5] = 2
+ * when mode 5 runs its form with single-dword transposer reads (the
+ * pair-read form spilled).
  * Errors: RX_EINVAL (NULL arguments). */
 int rx_program_jit_staging(const rx_program* prog, int32_t staged[6]);
 

@@ -775,6 +775,7 @@ struct JitKernel {
     hipFunction_t duo = nullptr;
     hipFunction_t split = nullptr;
     hipFunction_t skew = nullptr;
+    bool skew_words = false;   // skew is the single-dword-read form
     int dev = -1;
     int n_state = 0, n_ops = 0;
     std::string arch;
@@ -852,6 +853,7 @@ int jit_compile(Program* P, const char* arch_in) {
             if (hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, *f) != hipSuccess || scratch != 0)
                 *f = nullptr;
         }
+        K->skew_words = !K->skew && skew_w;
         if (!K->skew) K->skew = skew_w;   // the skewed kernel with single-dword transposer reads
         K->dev = dev;
     }
@@ -890,7 +892,7 @@ void jit_staging(const Program* P, int32_t staged[6]) {
     staged[2] = 1;
     staged[3] = K->duo ? 1 : 0;
     staged[4] = K->split ? 1 : 0;
-    staged[5] = K->skew ? 1 : 0;
+    staged[5] = K->skew ? (K->skew_words ? 2 : 1) : 0;
 }
 
 int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,
