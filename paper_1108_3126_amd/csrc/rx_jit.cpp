@@ -555,8 +555,7 @@ extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_split(const
 __device__ __forceinline__ void rx_gload(rx_v4& dst, const unsigned char* sp, u32 voff) {
     asm volatile("global_load_dwordx4 %0, %1, %2" : "=a"(dst) : "v"(voff), "s"(sp) : "memory");
 }
-// B = 0: every instruction but the last (nx[63]); B = 1: only that one;
-// B < 0: all of them.
+// B = 0: strings q < 16 (32 loads), B = 1: strings q >= 16, B < 0: all 64.
 template <int B>
 __device__ __forceinline__ void rx_issue_set(const unsigned char* __restrict__ bytes, long long length, long long n,
                                              long long sbase, int lane, long long off, rx_v4 (&nx)[64]) {
@@ -568,20 +567,22 @@ __device__ __forceinline__ void rx_issue_set(const unsigned char* __restrict__ b
         const u32 va = (u32)((lane & 31) * length + da), vb = (u32)((lane & 31) * length + db);
 #pragma unroll
         for (int q = 0; q < 32; ++q) {
+            if ((B == 0 && q >= 16) || (B == 1 && q < 16)) continue;
             const unsigned char* sp = bytes + (sbase + q * 32) * length + off;
-            if (B != 1) rx_gload(nx[q], sp, va);
-            if (B < 0 || (B == 0 && q < 31) || (B == 1 && q == 31)) rx_gload(nx[q + 32], sp, vb);
+            rx_gload(nx[q], sp, va);
+            rx_gload(nx[q + 32], sp, vb);
         }
     } else {
 #pragma unroll
         for (int q = 0; q < 32; ++q) {
+            if ((B == 0 && q >= 16) || (B == 1 && q < 16)) continue;
             long long bq = sbase + q * 32;
             if (bq > n - 1) bq = n - 1;
             long long r = lane & 31;
             if (r > n - 1 - bq) r = n - 1 - bq;
             const unsigned char* sp = bytes + bq * length + off;
-            if (B != 1) rx_gload(nx[q], sp, (u32)(r * length + da));
-            if (B < 0 || (B == 0 && q < 31) || (B == 1 && q == 31)) rx_gload(nx[q + 32], sp, (u32)(r * length + db));
+            rx_gload(nx[q], sp, (u32)(r * length + da));
+            rx_gload(nx[q + 32], sp, (u32)(r * length + db));
         }
     }
 }
@@ -669,7 +670,11 @@ __device__ __forceinline__ void rx_skew(const unsigned char* __restrict__ bytes,
     rx_init(s, acc);
     u32 acc_first = 0;
     rx_v4 nx[64];
-    rx_issue_set<-1>(bytes, length, n, sbase, lane, 0, nx);
+    // The first set's first burst is needed at once; the second set's half
+    // goes out now and half two ticks in, so the first set's requests reach
+    // memory ahead of it.
+    if (wave == 0) rx_issue_set<-1>(bytes, length, n, sbase, lane, 0, nx);
+    else rx_issue_set<0>(bytes, length, n, sbase, lane, 0, nx);
     // tick T: the transposing wave makes plane group T (first set: group T of
     // its string, second set: group T - 8), the circuit wave runs group T - 1
     rx_v2 raw[32];
@@ -687,14 +692,18 @@ __device__ __forceinline__ void rx_skew(const unsigned char* __restrict__ bytes,
                 }
             }
             // The registers are free once the burst's second half is in the
-            // tile.  A wave holds at most 63 loads in flight (a 64th would
-            // stall it until the first returns), so the last load of the
-            // burst waits two ticks.
+            // tile.  The next burst goes out in two halves, here and two
+            // ticks later: a wave may hold 63 loads in flight, and a wave
+            // whose requests back up in a busy memory system stalls at issue
+            // (holding the other wave at the next barrier), so shorter
+            // batches keep both waves computing.
             if (hh >= 0 && hh < nhalves && (hh & 1) == 1 && (hh >> 1) + 1 < nbursts)
                 rx_issue_set<0>(bytes, length, n, sbase, lane, ((hh >> 1) + 1) * 64, nx);
             __syncthreads();
         }
-        if ((T & 7) == 2 && T < nticks && hh >= 0 && hh < nhalves && (hh & 1) == 1 && (hh >> 1) + 1 < nbursts)
+        // (hh = -1: the second set's first burst, whose first half went out
+        // before the loop)
+        if ((T & 7) == 2 && T < nticks && hh >= -1 && hh < nhalves && (hh & 1) == 1 && (hh >> 1) + 1 < nbursts)
             rx_issue_set<1>(bytes, length, n, sbase, lane, ((hh >> 1) + 1) * 64, nx);
         if (wave == 1) {
             if (T < nticks) {
