@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1000000, help="strings the CPU oracle times")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--check", type=int, default=2000, help="sampled strings checked against the oracle")
-    ap.add_argument("--serving", type=int, default=1000, help="requests in the serving comparison (0 = skip)")
+    ap.add_argument("--serving", type=int, default=2000, help="requests per serving load point (0 = skip)")
     ap.add_argument("--copy-only", action="store_true", help="only run the stream-copy probe (counter calibration)")
     ap.add_argument("--serving-only", action="store_true", help="only run the serving comparison")
     ap.add_argument("--workload", choices=["single", "small", "multi", "pathological"], default="single",
@@ -335,6 +335,25 @@ def run_pathological(args, torch, dev):
             log(f"pathological {family} n={n_len}: {entry}")
         fam["ratio_1e4_1e3"] = round(fam["10000"]["ms"] / fam["1000"]["ms"], 2)
         fam["ratio_1e5_1e4"] = round(fam["100000"]["ms"] / fam["10000"]["ms"], 2)
+        # program size: k repetitions at n = 10^4 (time should grow with the set width)
+        scale = {}
+        s = W.pathological_strings(family, 10000, count=256)
+        d = torch.from_numpy(s.data).to(dev)
+        for kk in (1, 8, 64, k):
+            pk = W.pathological_program(family, kk)
+            pp = rx.compile(pk.ast, pk.root).upload(dev)
+            out = rx.match_fixed(pp, d, 10000, s.n)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rx.match_fixed(pp, d, 10000, s.n, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            scale[str(kk)] = {"nodes": int(len(pk.ast)), "words": int(pp.info.words), "ms": round(e0.elapsed_time(e1), 3),
+                              "closed_form_ok": bool(got[:128].sum() == 0 and got[128:].all())}
+        fam["k_scaling_n1e4"] = scale
+        log(f"pathological {family} k scaling at n=1e4: {scale}")
         res["families"][family] = fam
     return res
 
@@ -396,10 +415,8 @@ def run_serving(args, torch):
         want = oracle.match(p.ast, p.root, p.classes, p.search, s.data, s.offsets, index=idx)
         exact = exact and bool(np.array_equal(srv_out[k][idx], want))
 
-    rate = 0.9 * plain_cap
-    arrivals = W.poisson_arrivals(3, R, rate)
-
-    def run_plain_at_rate():
+    def run_plain_at_rate(rate):
+        arrivals = W.poisson_arrivals(3, R, rate)
         q, lat = queue.Queue(), []
 
         def worker():
@@ -421,9 +438,11 @@ def run_serving(args, torch):
             q.put((time.perf_counter(), r))
         q.put(None)
         th.join()
-        return np.array(lat) * 1e3
+        lat = np.array(lat) * 1e3
+        return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3)}
 
-    def run_server_at_rate():
+    def run_server_at_rate(rate):
+        arrivals = W.poisson_arrivals(3, R, rate)
         srv.reset_stats()
         ids = queue.Queue()
 
@@ -444,11 +463,25 @@ def run_serving(args, torch):
             ids.put(srv.submit(p, s.data, s.offsets))
         ids.put(None)
         th.join()
-        return srv.stats()
+        st = srv.stats()
+        return {"p50_ms": round(st["p50_us"] / 1e3, 3), "p99_ms": round(st["p99_us"] / 1e3, 3),
+                "steps": int(st["steps"])}
 
-    lp = run_plain_at_rate()
-    ss = run_server_at_rate()
+    # Poisson load points: half and 90% of each path's capacity.  The plain path
+    # cannot sustain the server's rates (its queue would grow without bound),
+    # so it is measured at its own two points only.
+    points = []
+    for who, cap in (("plain", plain_cap), ("batched", srv_cap)):
+        for frac in (0.5, 0.9):
+            rate = frac * cap
+            pt = {"load": f"{frac} x {who} capacity", "rate_req_per_s": round(rate, 1),
+                  "batched": run_server_at_rate(rate)}
+            if who == "plain":
+                pt["plain"] = run_plain_at_rate(rate)
+            points.append(pt)
+            log(f"serving point: {pt}")
     srv.close()
+    at = points[1]   # 0.9 x plain capacity: both paths at the same rate
     return {
         "requests": R,
         "mb": round(total_bytes / 1e6, 1),
@@ -456,11 +489,12 @@ def run_serving(args, torch):
         "batched_req_per_s": round(srv_cap, 1),
         "throughput_ratio": round(srv_cap / plain_cap, 2),
         "batched_GBs": round(total_bytes / (R / srv_cap) / 1e9, 3),
-        "rate_req_per_s": round(rate, 1),
-        "plain_p50_ms": round(float(np.percentile(lp, 50)), 3),
-        "plain_p99_ms": round(float(np.percentile(lp, 99)), 3),
-        "batched_p50_ms": round(ss["p50_us"] / 1e3, 3),
-        "batched_p99_ms": round(ss["p99_us"] / 1e3, 3),
+        "rate_req_per_s": at["rate_req_per_s"],
+        "plain_p50_ms": at["plain"]["p50_ms"],
+        "plain_p99_ms": at["plain"]["p99_ms"],
+        "batched_p50_ms": at["batched"]["p50_ms"],
+        "batched_p99_ms": at["batched"]["p99_ms"],
+        "points": points,
         "steps_at_capacity": int(st_cap["steps"]),
         "capacity_pack_ms": round(st_cap["pack_ms"], 2),
         "capacity_device_ms": round(st_cap["device_ms"], 2),

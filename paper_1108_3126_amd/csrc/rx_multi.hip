@@ -177,11 +177,26 @@ __global__ void k_bucket_clear(BucketArgs a) {
     }
 }
 
-__global__ void k_bucket_count(BucketArgs a) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int b = bucket_of(a.offsets[i + 1] - a.offsets[i], a.edges, a.n_edges);
-        atomicAdd(&a.counts[b], 1);
-    }
+// Each workgroup histograms a contiguous range of strings in LDS and adds
+// its totals to the global counts once per bucket (a global atomic per
+// string on ~16 counters serialises at the L2).
+__device__ __forceinline__ void wg_range(int64_t n, int64_t& r0, int64_t& r1) {
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    r0 = (int64_t)blockIdx.x * per;
+    r1 = r0 + per < n ? r0 + per : n;
+}
+
+__global__ __launch_bounds__(256) void k_bucket_count(BucketArgs a) {
+    __shared__ int32_t h[kMaxBuckets];
+    const int nb = a.n_edges + 1;
+    if (threadIdx.x < kMaxBuckets) h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t r0, r1;
+    wg_range(a.n, r0, r1);
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x)
+        atomicAdd(&h[bucket_of(a.offsets[i + 1] - a.offsets[i], a.edges, a.n_edges)], 1);
+    __syncthreads();
+    if (threadIdx.x < nb && h[threadIdx.x]) atomicAdd(&a.counts[threadIdx.x], h[threadIdx.x]);
 }
 
 // one thread: bucket starts, and where each bucket's items begin in the
@@ -226,11 +241,30 @@ __global__ void k_bucket_fill(BucketArgs a) {
     }
 }
 
-__global__ void k_bucket_scatter(BucketArgs a) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
+// The same ranges as k_bucket_count: a workgroup reserves its share of each
+// bucket with one global atomic, then places its strings through LDS
+// cursors.  The order of ids inside a bucket varies from run to run; every
+// string's bit is written at its own index, so results do not.
+__global__ __launch_bounds__(256) void k_bucket_scatter(BucketArgs a) {
+    __shared__ int32_t h[kMaxBuckets];
+    __shared__ int32_t g[kMaxBuckets];
+    const int nb = a.n_edges + 1;
+    if (threadIdx.x < kMaxBuckets) h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t r0, r1;
+    wg_range(a.n, r0, r1);
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x)
+        atomicAdd(&h[bucket_of(a.offsets[i + 1] - a.offsets[i], a.edges, a.n_edges)], 1);
+    __syncthreads();
+    if (threadIdx.x < nb) {
+        g[threadIdx.x] = h[threadIdx.x] ? atomicAdd(&a.cursor[threadIdx.x], h[threadIdx.x]) : 0;
+        h[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
         const int b = bucket_of(a.offsets[i + 1] - a.offsets[i], a.edges, a.n_edges);
-        const int32_t pos = atomicAdd(&a.cursor[b], 1);
-        a.ids[a.start[b] + pos] = (int32_t)i;
+        const int32_t pos = atomicAdd(&h[b], 1);
+        a.ids[a.start[b] + g[b] + pos] = (int32_t)i;
     }
 }
 
@@ -266,7 +300,7 @@ int launch_multi(const MultiArgs& m) {
     b.n_progs = m.n_progs;
     b.block_lines = m.block_lines;
     b.out_stride = m.n;
-    const int gs = (int)((m.n + 255) / 256 < 4096 ? (m.n + 255) / 256 : 4096);
+    const int gs = (int)((m.n + 255) / 256 < 1024 ? (m.n + 255) / 256 : 1024);
     hipLaunchKernelGGL(k_bucket_clear, dim3(1), dim3(64), 0, st, b);
     if (m.n > 0) hipLaunchKernelGGL(k_bucket_count, dim3(gs > 0 ? gs : 1), dim3(256), 0, st, b);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(64), 0, st, b);

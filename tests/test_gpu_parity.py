@@ -51,7 +51,7 @@ def test_small_seed0_all_variants(dev):
         assert np.array_equal(gpu_match(prog, s, dev, variant=v), want), v
 
 
-@pytest.mark.parametrize("block", range(0, 300, 50))
+@pytest.mark.parametrize("block", range(0, 1000, 50))
 def test_small_fuzz(dev, block):
     from paper_1108_3126_amd import rx
 
