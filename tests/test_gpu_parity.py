@@ -240,3 +240,33 @@ def test_sliced_pathological(dev):
     with pytest.raises(rx.RxError) as ei:
         rx.compile(big.ast, big.root).jit()
     assert ei.value.code == rx.RX_ETOOBIG
+
+
+def test_fixed_layout_fallbacks(dev):
+    """rx_match_fixed where the sliced kernel does not apply (length not a multiple of 16, a byte
+    buffer not 16-byte aligned, length 0) runs the table-form kernel; explicit sliced requests there
+    are refused with RX_EINVAL."""
+    from paper_1108_3126_amd import rx
+
+    prog = W.single_program(4)
+    p = rx.compile(prog.ast, prog.root, prog.classes, True).upload(dev).jit()
+    for length in (17, 40, 255):
+        s, _ = W.single_strings(prog, seed=length, n=3000, length=length, plant_frac=0.3)
+        want = oracle_match(prog, s)
+        d = torch.from_numpy(s.data).to(dev)
+        assert np.array_equal(fixed_match(p, s, length, dev), want), length
+        with pytest.raises(rx.RxError) as ei:
+            rx.match_fixed(p, d, length, s.n, launch=(rx.VARIANT_SLICED, 0, 0, 0))
+        assert ei.value.code == rx.RX_EINVAL
+    # a 16-byte length, but the strings start one byte into the buffer
+    s, _ = W.single_strings(prog, seed=9, n=3000, length=64, plant_frac=0.3)
+    want = oracle_match(prog, s)
+    buf = torch.zeros(s.data.size + 16, dtype=torch.uint8, device=dev)
+    buf[1:1 + s.data.size] = torch.from_numpy(s.data).to(dev)
+    out = rx.match_fixed(p, buf[1:1 + s.data.size], 64, s.n)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want)
+    # length 0: every string is empty; a searched non-nullable expression rejects them all
+    out = rx.match_fixed(p, torch.zeros(16, dtype=torch.uint8, device=dev), 0, 100)
+    torch.cuda.synchronize()
+    assert out.cpu().numpy().sum() == 0
