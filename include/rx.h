@@ -82,6 +82,32 @@ typedef struct {
     uint64_t bits[4];
 } rx_class;
 
+/*
+ * rx_parse -- regular-expression text into the AST rows rx_compile takes.
+ *
+ * The text form of the Section 2 grammar (bytes, concatenation, '|', '*',
+ * the empty string, parentheses) and the extensions of the node kinds above:
+ * '.' (every byte, newline included), bracket classes [abc] [a-z] [^...],
+ * the escapes \d \w \s \D \W \S (ASCII digits, word bytes, white space),
+ * \n \t \r \f \v \a \0 \xHH, any other non-alphanumeric byte after '\'
+ * standing for itself, '+', '?', and bounded repetition {m} {m,} {m,n} {,n}
+ * (n <= 1000), which expands into copies of the repeated expression (a node
+ * has one parent, Def. 4.2).  A '{' that does not open a well-formed bound is
+ * an ordinary byte.  Matching is of the whole string (or any substring with
+ * RX_SEARCH), so '^' and '$' are refused.  The pattern is len bytes, not
+ * NUL-terminated; bytes >= 0x80 are ordinary bytes.
+ *
+ * On success: ast[0 .. *n_ast) and classes[0 .. *n_classes) hold the tree,
+ * *root its root.  If ast_cap or class_cap is too small the call returns
+ * RX_ETOOBIG with *n_ast and *n_classes set to the sizes needed (ast and
+ * classes may be NULL when their capacity is 0), so a caller can size its
+ * buffers with a first call.  Errors: RX_EINVAL (syntax; the message gives
+ * the byte position), RX_ETOOBIG (buffers, or more than 2^20 nodes after
+ * expanding repetitions).
+ */
+int rx_parse(const char* pattern, size_t len, rx_ast_node* ast, int32_t ast_cap, int32_t* n_ast, int32_t* root,
+             rx_class* classes, int32_t class_cap, int32_t* n_classes);
+
 /* One node of a compiled program's node array d[] (the heap of Def. 4.1).
  * label: the byte of a BYTE leaf, the class index of a CLASS leaf (the search
  * wrapper's any-byte class is appended after the caller's classes), -1

@@ -98,6 +98,8 @@ SIGNATURES = {
     "rx_program_jit_source": (ctypes.c_int, [_VP, ctypes.c_char_p, _SZ, ctypes.POINTER(_SZ)]),
     "rx_program_jit_stats": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "rx_program_jit_staging": (ctypes.c_int, [_VP, ctypes.POINTER(_I32)]),
+    "rx_parse": (ctypes.c_int, [ctypes.c_char_p, _SZ, _VP, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _VP, _I32,
+                                ctypes.POINTER(_I32)]),
     "rx_match_multi_workspace": (ctypes.c_int64, [_I64, _I32, ctypes.POINTER(rx_multi_config)]),
     "rx_match_multi": (ctypes.c_int, [ctypes.POINTER(_VP), _I32, _VP, _VP, _I64, _VP, _VP, _SZ,
                                       ctypes.POINTER(rx_multi_config), _VP]),
@@ -263,6 +265,27 @@ class Program:
 
 
 def compile(ast, root, classes=None, search=False) -> Program:
+    return Program(ast, root, classes, search)
+
+
+def parse(pattern):
+    """Regular-expression text (str or bytes; see rx_parse) -> (ast, root, classes) for compile()."""
+    pat = pattern.encode("latin-1") if isinstance(pattern, str) else bytes(pattern)
+    n_ast, root, n_cls = _I32(), _I32(), _I32()
+    rc = lib().rx_parse(pat, len(pat), None, 0, ctypes.byref(n_ast), ctypes.byref(root), None, 0, ctypes.byref(n_cls))
+    if rc not in (RX_OK, RX_ETOOBIG) or (rc == RX_ETOOBIG and n_ast.value == 0):
+        _check(rc)
+    ast = np.zeros(n_ast.value, dtype=AST_DTYPE)
+    classes = np.zeros((n_cls.value, 4), dtype=np.uint64)
+    _check(lib().rx_parse(pat, len(pat), ast.ctypes.data_as(ctypes.c_void_p), n_ast.value, ctypes.byref(n_ast),
+                          ctypes.byref(root), classes.ctypes.data_as(ctypes.c_void_p), n_cls.value,
+                          ctypes.byref(n_cls)))
+    return ast, root.value, classes
+
+
+def compile_regex(pattern, search=False) -> Program:
+    """compile(parse(pattern)): whole-string matching, or any substring with search=True."""
+    ast, root, classes = parse(pattern)
     return Program(ast, root, classes, search)
 
 

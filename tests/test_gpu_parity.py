@@ -270,3 +270,31 @@ def test_fixed_layout_fallbacks(dev):
     out = rx.match_fixed(p, torch.zeros(16, dtype=torch.uint8, device=dev), 0, 100)
     torch.cuda.synchronize()
     assert out.cpu().numpy().sum() == 0
+
+
+def test_parsed_patterns_on_gpu(dev):
+    """Regular-expression text through rx_parse, matched on the GPU (table form and the sliced circuit),
+    against Python's re on bytes with DOTALL."""
+    import re
+
+    from paper_1108_3126_amd import rx
+
+    pats = [b"a(b|c)*d", b"(a|aa)*b", b"x{2,3}y{,2}z{2}", b"[^a-c]+\\d?", b"\\w+@\\w+\\.com", b"(|a)(b|)",
+            b"(ab){0,4}c+", b"[a-c]*1[\\x30-\\x39]{2}", b".\\..", b"((a*)*)*b"]
+    rng = np.random.default_rng(77)
+    alphabet = np.frombuffer(b"abcdx1.@\n", np.uint8)
+    strings = [bytes(alphabet[rng.integers(0, len(alphabet), size=rng.integers(0, 20))]) for _ in range(2000)]
+    strings += [b"abcbd", b"aaab", b"xxyzz", b"u_1@host.com", b"abababc", b"ab112"]
+    s = W.pack(strings)
+    fixed = [bytes(alphabet[rng.integers(0, len(alphabet), size=32)]) for _ in range(2048)]
+    fs = W.pack(fixed)
+    for pat in pats:
+        r = re.compile(pat, re.DOTALL)
+        for search in (False, True):
+            f = r.search if search else r.fullmatch
+            want = np.array([1 if f(w) else 0 for w in strings], np.uint8)
+            p = rx.compile_regex(pat, search=search).upload(dev)
+            assert np.array_equal(gpu_match(None, s, dev, p=p), want), (pat, search)
+            p.jit()
+            want = np.array([1 if f(w) else 0 for w in fixed], np.uint8)
+            assert np.array_equal(fixed_match(p, fs, 32, dev), want), (pat, search, "sliced")
