@@ -223,6 +223,19 @@ typedef struct {
                                0 = 5 when its kernel was kept, else 3, else 2. */
 } rx_launch;
 
+/* Earliest accepting prefix (the accept bit's first appearance, Def. 5.3
+ * applied to every prefix): d_first[i] = the smallest k in [0, len_i] such
+ * that the first k bytes of string i are accepted, or -1 if no prefix is.
+ * With RX_SEARCH this is the end offset of the match that ends first; without
+ * it, the length of the shortest prefix in the language (k = len_i is a
+ * whole-string match only when no shorter prefix matched).  Strings and
+ * offsets as for rx_match; d_first is int64[n] on the device.  Runs the
+ * table-form kernels (one lane per string up to 16 words, else one
+ * wavefront per string), stopping each string at its first accept.  Errors
+ * as rx_match. */
+int rx_match_first(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t n,
+                   int64_t* d_first, void* stream);
+
 /* rx_match with an explicit kernel variant and launch shape (the autotuner's
  * entry point).  Every variant returns the same bits (Thm. 7.2: the parallel
  * schedule does not change the result). */

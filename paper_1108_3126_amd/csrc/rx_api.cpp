@@ -197,6 +197,30 @@ int rx_match(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_of
     return rx_match_ex(prog, d_bytes, d_offsets, n, d_out, nullptr, stream);
 }
 
+int rx_match_first(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t n,
+                   int64_t* d_first, void* stream) {
+    RX_GUARD_BEGIN
+    LaunchArgs a;
+    // the result bytes are not written: pass the position buffer through the checks
+    if (int rc = make_launch_args(reinterpret_cast<const Program*>(prog), d_bytes, d_offsets, n,
+                                  reinterpret_cast<uint8_t*>(d_first), stream, &a))
+        return rc;
+    if (n == 0) return RX_OK;
+    const Program* P = reinterpret_cast<const Program*>(prog);
+    a.out = nullptr;
+    a.first_pos = d_first;
+    int e;
+    if (P->W <= kLaneMaxWords) {
+        e = launch_lane(a);
+    } else {
+        if (P->W > kWaveMaxWords) return fail(RX_ETOOBIG, "the wavefront kernel holds sets of at most 128 words");
+        e = launch_wave(a);
+    }
+    if (e) return hip_fail(e, "kernel launch");
+    return RX_OK;
+    RX_GUARD_END
+}
+
 int rx_match_fixed_ex(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int64_t n, uint8_t* d_out,
                       const rx_launch* launch, void* stream) {
     RX_GUARD_BEGIN

@@ -145,6 +145,7 @@ struct LaunchArgs {
     uint8_t* out;
     int32_t block, grid, unroll;
     void* stream;
+    int64_t* first_pos = nullptr;   // rx_match_first: earliest accepting prefix per string (out unused)
 };
 int launch_lane(const LaunchArgs& a);
 // bit-sliced node circuit (rx_jit.cpp)

@@ -39,6 +39,7 @@ struct KArgs {
     int64_t stride;
     int64_t n;
     uint8_t* out;
+    int64_t* first_pos;   // FIRST kernels: the earliest accepting prefix length, -1 if none
 };
 
 template <int W>
@@ -81,7 +82,9 @@ __device__ __forceinline__ void lane_step(uint32_t (&S)[W], uint32_t c, const ui
     }
 }
 
-template <int W>
+// FIRST: instead of the result bit, the smallest k such that the accept bit
+// is in S after the first k bytes (k = 0: the root is nullable), or -1.
+template <int W, bool FIRST>
 __global__ __launch_bounds__(256) void k_lane(KArgs a) {
     extern __shared__ uint32_t lds[];
     uint32_t* M = lds;
@@ -99,23 +102,31 @@ __global__ __launch_bounds__(256) void k_lane(KArgs a) {
         const int64_t lo = a.offsets ? a.offsets[sid] : sid * a.stride;
         const int64_t hi = a.offsets ? a.offsets[sid + 1] : lo + a.stride;
         int res = -1;
+        int64_t pos = (FIRST && (pick<W>(S, aw) & abit)) ? 0 : -1;
         // aligned 16-byte blocks of the absolute address range [bytes+lo, bytes+hi):
         // every block read holds at least one byte of the string
         const int64_t skew = (int64_t)(reinterpret_cast<uintptr_t>(a.bytes) & 15);
-        for (int64_t base = ((lo + skew) & ~int64_t(15)) - skew; base < hi; base += 16) {
+        for (int64_t base = ((lo + skew) & ~int64_t(15)) - skew; base < hi && pos < 0; base += 16) {
             const uint4 v = *reinterpret_cast<const uint4*>(a.bytes + base);
             const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
             const int b0 = lo > base ? (int)(lo - base) : 0;
             const int b1 = hi - base < 16 ? (int)(hi - base) : 16;
 #pragma unroll
             for (int b = 0; b < 16; ++b) {
-                if (b >= b0 && b < b1) lane_step<W>(S, (wv[b >> 2] >> (8 * (b & 3))) & 255u, M, F);
+                if (b >= b0 && b < b1 && (!FIRST || pos < 0)) {
+                    lane_step<W>(S, (wv[b >> 2] >> (8 * (b & 3))) & 255u, M, F);
+                    if (FIRST && (pick<W>(S, aw) & abit)) pos = base + b + 1 - lo;
+                }
             }
             uint32_t any = 0;
 #pragma unroll
             for (int w = 0; w < W; ++w) any |= S[w];
             if (any == 0) { res = 0; break; }                          // no live thread: reject
-            if (a.suffix_any && (pick<W>(S, aw) & abit)) { res = 1; break; }  // accept is absorbing
+            if (!FIRST && a.suffix_any && (pick<W>(S, aw) & abit)) { res = 1; break; }  // accept is absorbing
+        }
+        if (FIRST) {
+            a.first_pos[sid] = pos;
+            continue;
         }
         if (res < 0) res = (pick<W>(S, aw) & abit) ? 1 : 0;
         a.out[sid] = (uint8_t)res;
@@ -123,7 +134,7 @@ __global__ __launch_bounds__(256) void k_lane(KArgs a) {
 }
 
 // One wavefront per string.  Lane j owns words j and j + 64 of the set.
-template <bool TABLES_IN_LDS>
+template <bool TABLES_IN_LDS, bool FIRST>
 __global__ __launch_bounds__(1024) void k_wave(KArgs a) {
     extern __shared__ uint32_t lds[];
     const int W = a.W, L = a.L;
@@ -150,12 +161,17 @@ __global__ __launch_bounds__(1024) void k_wave(KArgs a) {
         const int64_t lo = a.offsets ? a.offsets[sid] : sid * a.stride;
         const int64_t hi = a.offsets ? a.offsets[sid + 1] : lo + a.stride;
         int res = -1;
+        int64_t pos = -1;
+        if (FIRST) {
+            const uint32_t sw = (uint32_t)__builtin_amdgcn_readlane((int)(aw < 64 ? S0 : S1), aw & 63);
+            if (sw & abit) pos = 0;
+        }
         const int64_t skew = (int64_t)(reinterpret_cast<uintptr_t>(a.bytes) & 3);
-        for (int64_t base = ((lo + skew) & ~int64_t(3)) - skew; base < hi && res < 0; base += 4) {
+        for (int64_t base = ((lo + skew) & ~int64_t(3)) - skew; base < hi && res < 0 && pos < 0; base += 4) {
             const uint32_t word = *reinterpret_cast<const uint32_t*>(a.bytes + base);
             const int b0 = lo > base ? (int)(lo - base) : 0;
             const int b1 = hi - base < 4 ? (int)(hi - base) : 4;
-            for (int b = b0; b < b1; ++b) {
+            for (int b = b0; b < b1 && pos < 0; ++b) {
                 const uint32_t c = (word >> (8 * b)) & 255u;
                 const uint32_t X0 = own0 ? (S0 & M[c * W + lane]) : 0u;
                 const uint32_t X1 = own1 ? (S1 & M[c * W + 64 + lane]) : 0u;
@@ -189,13 +205,21 @@ __global__ __launch_bounds__(1024) void k_wave(KArgs a) {
                 }
                 S0 = N0;
                 S1 = N1;
+                if (FIRST) {
+                    const uint32_t sw = (uint32_t)__builtin_amdgcn_readlane((int)(aw < 64 ? S0 : S1), aw & 63);
+                    if (sw & abit) pos = base + b + 1 - lo;
+                }
             }
             const bool live = __ballot((S0 | S1) != 0) != 0;
             if (!live) { res = 0; break; }
-            if (a.suffix_any) {
+            if (!FIRST && a.suffix_any) {
                 const uint32_t sw = (uint32_t)__builtin_amdgcn_readlane((int)(aw < 64 ? S0 : S1), aw & 63);
                 if (sw & abit) { res = 1; break; }
             }
+        }
+        if (FIRST) {
+            if (lane == 0) a.first_pos[sid] = pos;
+            continue;
         }
         if (res < 0) {
             const uint32_t sw = (uint32_t)__builtin_amdgcn_readlane((int)(aw < 64 ? S0 : S1), aw & 63);
@@ -220,6 +244,7 @@ KArgs kargs(const LaunchArgs& a) {
     k.stride = a.stride;
     k.n = a.n;
     k.out = a.out;
+    k.first_pos = a.first_pos;
     return k;
 }
 
@@ -230,7 +255,10 @@ int launch_lane_w(const LaunchArgs& a) {
     int grid = a.grid > 0 ? a.grid : (int)(need < (1 << 30) ? need : (1 << 30));
     if (grid < 1) grid = 1;
     const size_t lds = 4 * (size_t)(256 + a.L) * W;
-    hipLaunchKernelGGL(k_lane<W>, dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
+    if (a.first_pos)
+        hipLaunchKernelGGL((k_lane<W, true>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
+    else
+        hipLaunchKernelGGL((k_lane<W, false>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
     return (int)hipGetLastError();
 }
 
@@ -258,12 +286,20 @@ int launch_wave(const LaunchArgs& a) {
     if (lds <= 150 * 1024) {
         static bool attr_set = false;
         if (!attr_set) {
-            hipFuncSetAttribute((const void*)k_wave<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            hipFuncSetAttribute((const void*)k_wave<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024);
+            hipFuncSetAttribute((const void*)k_wave<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024);
             attr_set = true;
         }
-        hipLaunchKernelGGL(k_wave<true>, dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
+        if (a.first_pos)
+            hipLaunchKernelGGL((k_wave<true, true>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
+        else
+            hipLaunchKernelGGL((k_wave<true, false>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
+    } else if (a.first_pos) {
+        hipLaunchKernelGGL((k_wave<false, true>), dim3(grid), dim3(block), 0, (hipStream_t)a.stream, kargs(a));
     } else {
-        hipLaunchKernelGGL(k_wave<false>, dim3(grid), dim3(block), 0, (hipStream_t)a.stream, kargs(a));
+        hipLaunchKernelGGL((k_wave<false, false>), dim3(grid), dim3(block), 0, (hipStream_t)a.stream, kargs(a));
     }
     return (int)hipGetLastError();
 }

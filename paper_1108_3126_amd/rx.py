@@ -98,6 +98,7 @@ SIGNATURES = {
     "rx_program_jit_source": (ctypes.c_int, [_VP, ctypes.c_char_p, _SZ, ctypes.POINTER(_SZ)]),
     "rx_program_jit_stats": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "rx_program_jit_staging": (ctypes.c_int, [_VP, ctypes.POINTER(_I32)]),
+    "rx_match_first": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _VP]),
     "rx_parse": (ctypes.c_int, [ctypes.c_char_p, _SZ, _VP, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _VP, _I32,
                                 ctypes.POINTER(_I32)]),
     "rx_match_multi_workspace": (ctypes.c_int64, [_I64, _I32, ctypes.POINTER(rx_multi_config)]),
@@ -313,6 +314,27 @@ def match(prog: Program, data, offsets, out=None, launch=None, stream=None):
         L = launch if isinstance(launch, rx_launch) else rx_launch(*launch)
         _check(lib().rx_match_ex(prog.handle, dptr, ctypes.c_void_p(offsets.data_ptr()), n,
                                  ctypes.c_void_p(out.data_ptr()), ctypes.byref(L), sh))
+    return out
+
+
+def match_first(prog: Program, data, offsets, out=None, stream=None):
+    """Earliest accepting prefix length per string (int64 tensor, -1 where no prefix matches)."""
+    import torch
+
+    if prog._dev_buf is None:
+        prog.upload(device=data.device if data.numel() else offsets.device, stream=stream)
+    if data.dtype != torch.uint8 or offsets.dtype != torch.int64:
+        raise TypeError("data must be uint8 and offsets int64")
+    if not (data.is_cuda and offsets.is_cuda):
+        raise TypeError("data and offsets must be device tensors")
+    data = data.contiguous()
+    offsets = offsets.contiguous()
+    n = offsets.numel() - 1
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.int64, device=offsets.device)
+    dptr = ctypes.c_void_p(data.data_ptr() if data.numel() else offsets.data_ptr())
+    _check(lib().rx_match_first(prog.handle, dptr, ctypes.c_void_p(offsets.data_ptr()), n,
+                                ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
 
 

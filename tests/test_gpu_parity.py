@@ -298,3 +298,95 @@ def test_parsed_patterns_on_gpu(dev):
             p.jit()
             want = np.array([1 if f(w) else 0 for w in fixed], np.uint8)
             assert np.array_equal(fixed_match(p, fs, 32, dev), want), (pat, search, "sliced")
+
+
+def _first_by_prefixes(prog, strings, search):
+    """Earliest accepting prefix by brute force: the oracle on every prefix of every string."""
+    pre, owner, plen = [], [], []
+    for i, w in enumerate(strings):
+        for k in range(len(w) + 1):
+            pre.append(w[:k])
+            owner.append(i)
+            plen.append(k)
+    ps = W.pack(pre)
+    acc = oracle.match(prog.ast, prog.root, prog.classes, search, ps.data, ps.offsets)
+    first = np.full(len(strings), -1, np.int64)
+    for a, i, k in zip(acc, owner, plen):
+        if a and first[i] < 0:
+            first[i] = k
+    return first
+
+
+def _gpu_first(p, strings, dev):
+    from paper_1108_3126_amd import rx
+
+    s = W.pack(strings)
+    d = torch.from_numpy(s.data if s.data.size else np.zeros(1, np.uint8)).to(dev)
+    out = rx.match_first(p, d, torch.from_numpy(s.offsets).to(dev))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_match_first_small_programs(dev):
+    from paper_1108_3126_amd import rx
+
+    for seed in range(60):
+        prog = W.small_program(seed)
+        s = W.small_strings(seed)
+        strings = [bytes(s.data[s.offsets[i]:s.offsets[i + 1]]) for i in range(200)]
+        for search in (False, True):
+            prog.search = search
+            p = rx.compile(prog.ast, prog.root, prog.classes, search).upload(dev)
+            want = _first_by_prefixes(prog, strings, search)
+            got = _gpu_first(p, strings, dev)
+            assert np.array_equal(got, want), (seed, search, np.nonzero(got != want)[0][:5])
+
+
+def test_match_first_single_program(dev):
+    from paper_1108_3126_amd import rx
+
+    prog = W.single_program(1)
+    s, planted = W.single_strings(prog, seed=33, n=240, length=256, plant_frac=0.5)
+    strings = [bytes(s.data[s.offsets[i]:s.offsets[i + 1]]) for i in range(s.n)]
+    p = rx.compile(prog.ast, prog.root, prog.classes, True).upload(dev)
+    want = _first_by_prefixes(prog, strings, True)
+    got = _gpu_first(p, strings, dev)
+    assert (got[planted] >= 0).all()
+    assert np.array_equal(got, want)
+    # the result bit of a searched program is "some prefix is accepted"
+    bits = gpu_match(prog, s, dev, p=p)
+    assert np.array_equal(bits, (got >= 0).astype(np.uint8))
+
+
+def test_match_first_wavefront_programs(dev):
+    """Programs above 16 words run one wavefront per string: brute force on short strings, the
+    closed form (a^n rejected, a^(n-1) t accepted exactly at its end) on long ones."""
+    from paper_1108_3126_amd import rx
+
+    for family, k in (("nested", 819), ("altstar", 585)):
+        prog = W.pathological_program(family, k)
+        p = rx.compile(prog.ast, prog.root).upload(dev)
+        assert p.info.words > 16
+        short = W.pathological_strings(family, 24, count=8)
+        strings = [bytes(short.data[short.offsets[i]:short.offsets[i + 1]]) for i in range(short.n)]
+        assert np.array_equal(_gpu_first(p, strings, dev), _first_by_prefixes(prog, strings, False)), family
+        long = W.pathological_strings(family, 3000, count=64)
+        strings = [bytes(long.data[long.offsets[i]:long.offsets[i + 1]]) for i in range(long.n)]
+        got = _gpu_first(p, strings, dev)
+        assert (got[:32] == -1).all() and (got[32:] == 3000).all(), family
+
+
+def test_match_first_parsed_patterns_against_re(dev):
+    """Searched: the end of the match that ends first, against Python re on every prefix."""
+    import re
+
+    from paper_1108_3126_amd import rx
+
+    rng = np.random.default_rng(5)
+    alphabet = np.frombuffer(b"abcx1", np.uint8)
+    strings = [bytes(alphabet[rng.integers(0, len(alphabet), size=rng.integers(0, 24))]) for _ in range(400)]
+    for pat in (b"b(a|c)+x", b"(ab|ba){2}", b"c[ab]*1", b"x?1+", b"a(b|)c"):
+        r = re.compile(pat, re.DOTALL)
+        want = np.array([next((k for k in range(len(w) + 1) if r.search(w[:k])), -1) for w in strings], np.int64)
+        p = rx.compile_regex(pat, search=True).upload(dev)
+        assert np.array_equal(_gpu_first(p, strings, dev), want), pat
