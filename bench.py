@@ -152,25 +152,36 @@ def main():
     log(f"check: {len(sample)} sampled strings bit-exact={bit_exact}, planted all matched={planted_ok}, "
         f"accepted {int(got.sum())}/{strings.n}")
 
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    # The timed region: K launches back to back on the launch stream, one HIP
+    # event before and one after (an event between launches costs several us
+    # of wall time per step).  The average launch duration is the region's
+    # event time over K, gaps between launches included.
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
+    ev0.record()
     for i in range(args.steps):
-        starts[i].record()
         step(args.warmup + i)
-        ends[i].record()
+    ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    kern_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    avg_kernel_ms = ev0.elapsed_time(ev1) / args.steps
     ms_per_step = wall * 1e3 / args.steps
     input_bytes = int(strings.offsets[-1])
     value = input_bytes / (ms_per_step * 1e-3) / 1e9
-    avg_kernel_ms = float(np.mean(kern_ms))
     algo_bytes = input_bytes + strings.n + (8 * (strings.n + 1) if args.layout == "offsets" else 0)
     achieved = algo_bytes / (avg_kernel_ms * 1e-3) / 1e9
-    log(f"kernel ms: mean {avg_kernel_ms:.4f} median {np.median(kern_ms):.4f} min {min(kern_ms):.4f}; "
-        f"wall ms/step {ms_per_step:.4f}")
+    # spread of single launches (after the timed region; not used for the figures)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(10)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(10)]
+    for i in range(10):
+        starts[i].record()
+        step(i)
+        ends[i].record()
+    torch.cuda.synchronize()
+    kern_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    log(f"timed region: {avg_kernel_ms:.4f} ms per launch (events), wall {ms_per_step:.4f} ms/step; "
+        f"single launches: median {np.median(kern_ms):.4f} min {min(kern_ms):.4f}")
 
     cpu = None
     if not args.no_cpu:
