@@ -34,7 +34,7 @@ def kernel_id(p, launch_desc: str) -> str:
 
     src = p.jit_source() if p.jit_stats()["ready"] else "table-form"
     # the default staging mode and the form it runs (other modes do not run here)
-    st = p.jit_staging() if p.jit_stats()["ready"] else [0] * 6
+    st = p.jit_staging() if p.jit_stats()["ready"] else [0] * 7
     form = f"mode={st[0]}/{st[st[0]]}"
     return hashlib.sha256((src + "|" + launch_desc + "|" + form).encode()).hexdigest()[:16]
 

@@ -236,6 +236,15 @@ typedef struct {
 int rx_match_first(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t n,
                    int64_t* d_first, void* stream);
 
+/* rx_match_first for fixed-length strings (string i = d_bytes[i*length,
+ * (i+1)*length)).  With a compiled circuit (rx_program_jit), 16-byte aligned
+ * bytes and length % 16 == 0 (length <= 2^26), the skewed bit-sliced kernel
+ * runs, recording each string's first accept as it appears; otherwise the
+ * table-form kernels.  A program whose root is nullable answers 0 for every
+ * string without matching.  Errors as rx_match_fixed. */
+int rx_match_first_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int64_t n,
+                         int64_t* d_first, void* stream);
+
 /* rx_match with an explicit kernel variant and launch shape (the autotuner's
  * entry point).  Every variant returns the same bits (Thm. 7.2: the parallel
  * schedule does not change the result). */
@@ -287,9 +296,11 @@ int rx_program_jit_stats(const rx_program* prog, int32_t* ready, int32_t* state_
  * is compiled; staged[0] = the mode that unroll = 0 selects.  All zero before
  * rx_program_jit, or where the program has no loaded kernel.  staged[5] = 2
  * when mode 5 runs its form with single-dword transposer reads (the
- * pair-read form spilled).
+ * pair-read form spilled).  staged[6] describes the earliest-accept form of
+ * the mode-5 kernel that rx_match_first_fixed runs: 1 pair reads, 2
+ * single-dword reads, 0 dropped (the table-form kernels run instead).
  * Errors: RX_EINVAL (NULL arguments). */
-int rx_program_jit_staging(const rx_program* prog, int32_t staged[6]);
+int rx_program_jit_staging(const rx_program* prog, int32_t staged[7]);
 
 /* Length bucketing and launch shape of rx_match_multi; zero fields mean default. */
 typedef struct {

@@ -197,6 +197,44 @@ int rx_match(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_of
     return rx_match_ex(prog, d_bytes, d_offsets, n, d_out, nullptr, stream);
 }
 
+int rx_match_first_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int64_t n,
+                         int64_t* d_first, void* stream) {
+    RX_GUARD_BEGIN
+    const Program* P = reinterpret_cast<const Program*>(prog);
+    if (!P) return fail(RX_EINVAL, "program is NULL");
+    if (length < 0) return fail(RX_EINVAL, "negative length");
+    if (n < 0) return fail(RX_EINVAL, "negative string count");
+    if (n > 0 && (!d_first || (length > 0 && !d_bytes))) return fail(RX_EINVAL, "NULL device buffer");
+    if (!P->dev) return fail(RX_ENOTUPLOADED, "program has not been uploaded (rx_program_upload)");
+    if (n == 0) return RX_OK;
+    int e;
+    if (P->nullable) {
+        e = launch_fill_i64(d_first, n, 0, stream);   // the empty prefix is accepted
+    } else if (jit_first_ready(P) && length > 0 && (length % 16) == 0 && length <= (1 << 26) &&
+               (reinterpret_cast<uintptr_t>(d_bytes) & 15) == 0) {
+        e = launch_sliced_first(P, d_bytes, length, n, d_first, stream);
+    } else {
+        LaunchArgs a;
+        if (int rc = make_launch_args(P, d_bytes ? d_bytes : reinterpret_cast<const uint8_t*>(d_first),
+                                      reinterpret_cast<const int64_t*>(d_first), n,
+                                      reinterpret_cast<uint8_t*>(d_first), stream, &a))
+            return rc;
+        a.offsets = nullptr;
+        a.stride = length;
+        a.out = nullptr;
+        a.first_pos = d_first;
+        if (P->W <= kLaneMaxWords) {
+            e = launch_lane(a);
+        } else {
+            if (P->W > kWaveMaxWords) return fail(RX_ETOOBIG, "the wavefront kernel holds sets of at most 128 words");
+            e = launch_wave(a);
+        }
+    }
+    if (e) return hip_fail(e, "kernel launch");
+    return RX_OK;
+    RX_GUARD_END
+}
+
 int rx_match_first(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t n,
                    int64_t* d_first, void* stream) {
     RX_GUARD_BEGIN
@@ -429,7 +467,7 @@ int rx_program_jit_stats(const rx_program* prog, int32_t* ready, int32_t* state_
     return RX_OK;
 }
 
-int rx_program_jit_staging(const rx_program* prog, int32_t staged[6]) {
+int rx_program_jit_staging(const rx_program* prog, int32_t staged[7]) {
     if (!prog || !staged) return fail(RX_EINVAL, "NULL argument");
     jit_staging(reinterpret_cast<const Program*>(prog), staged);
     return RX_OK;

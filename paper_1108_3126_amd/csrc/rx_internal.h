@@ -155,9 +155,15 @@ int jit_compile(Program* P, const char* arch);
 void jit_free(Program* P);
 bool jit_ready(const Program* P, int* n_state, int* n_ops);
 // staged[u] for staging modes u = 0..5 (see rx_program_jit_staging).
-void jit_staging(const Program* P, int32_t staged[6]);
+void jit_staging(const Program* P, int32_t staged[7]);
 // The staging mode that unroll = 0 selects.
 int jit_default_staging(const Program* P);
+// The skewed kernel's earliest-accept form (kept unless it spills) and its launch.
+bool jit_first_ready(const Program* P);
+int launch_sliced_first(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, int64_t* first,
+                        void* stream);
+// first[i] = value for i < n (a fill kernel, no memset)
+int launch_fill_i64(int64_t* first, int64_t n, int64_t value, void* stream);
 int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,
                         int burst, void* stream);
 int launch_wave(const LaunchArgs& a);

@@ -34,6 +34,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "rx_internal.h"
@@ -499,6 +500,44 @@ __device__ __forceinline__ void rx_run_planes(const u32* slot, int lane, u32 (&s
     rx_step(s, acc, w[24], w[25], w[26], w[27], w[28], w[29], w[30], w[31]);
 }
 
+// As rx_run_planes, also recording each string's earliest accept.  After the
+// step that consumes byte k0 + t (t = 0..3) of the first set's strings (bits
+// 0-15) and byte k1 + t of the second set's (bits 16-31), bits of vmask whose
+// accept appears for the first time get first[string] = that count + 1.
+__device__ __forceinline__ void rx_note_first(u32 nw, int t, long long k0, long long k1, long long base, long long n,
+                                              int lane, long long* __restrict__ first) {
+    while (nw) {
+        const int j = __builtin_ctz(nw);
+        nw &= nw - 1;
+        const long long sid = base + j * 64 + lane;
+        if (sid < n) first[sid] = (j < 16 ? k0 : k1) + t + 1;
+    }
+}
+__device__ __forceinline__ void rx_run_planes_first(const u32* slot, int lane, u32 (&s)[RX_NS], u32& acc, u32& seen,
+                                                    u32 vmask, long long k0, long long k1, long long base,
+                                                    long long n, long long* __restrict__ first) {
+    const rx_v4* q = reinterpret_cast<const rx_v4*>(slot);
+    u32 w[32];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const rx_v4 v = q[k * 64 + lane];
+        w[4 * k] = v.x;
+        w[4 * k + 1] = v.y;
+        w[4 * k + 2] = v.z;
+        w[4 * k + 3] = v.w;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        rx_step(s, acc, w[8 * t], w[8 * t + 1], w[8 * t + 2], w[8 * t + 3], w[8 * t + 4], w[8 * t + 5], w[8 * t + 6],
+                w[8 * t + 7]);
+        const u32 nw = acc & ~seen & vmask;
+        if (nw) {
+            seen |= nw;
+            rx_note_first(nw, t, k0, k1, base, n, lane, first);
+        }
+    }
+}
+
 // length must be a multiple of 16 (whole 4-position groups, whole 16-byte loads).
 extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_split(const unsigned char* __restrict__ bytes,
         long long length, long long n, unsigned char* __restrict__ out) {
@@ -653,9 +692,10 @@ __device__ __forceinline__ void rx_pairs_to_planes(const rx_v2 (&raw)[32], u32* 
 
 // length must be a multiple of 16.  PAIRS: the transposing wave reads dword
 // pairs (fewer LDS accesses, 64 more registers) rather than single dwords.
-template <bool PAIRS>
+template <bool PAIRS, bool FIRST>
 __device__ __forceinline__ void rx_skew(const unsigned char* __restrict__ bytes, long long length, long long n,
-                                        unsigned char* __restrict__ out, u32* rx_tile) {
+                                        unsigned char* __restrict__ out, long long* __restrict__ first,
+                                        u32* rx_tile) {
     u32* rx_ring = rx_tile + RX_WAVE_STRINGS * 8;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -669,6 +709,7 @@ __device__ __forceinline__ void rx_skew(const unsigned char* __restrict__ bytes,
     u32 acc;
     rx_init(s, acc);
     u32 acc_first = 0;
+    u32 seen = 0;   // FIRST: strings whose accept has appeared
     rx_v4 nx[64];
     // The first set's first burst is needed at once; the second set's half
     // goes out now and half two ticks in, so the first set's requests reach
@@ -727,25 +768,55 @@ __device__ __forceinline__ void rx_skew(const unsigned char* __restrict__ bytes,
                 for (int i = 0; i < RX_NS; ++i) s[i] = (s[i] & 0x0000ffffu) | (s0[i] & 0xffff0000u);
                 acc = (acc & 0x0000ffffu) | (a0 & 0xffff0000u);
             }
-            rx_run_planes(rx_ring + (int)(P & 1) * RX_SLOT_WORDS, lane, s, acc);
+            if (FIRST) {
+                // the first set is real for groups [0, ngroups), the second from group 8 on
+                const u32 vmask = (P < ngroups ? 0x0000ffffu : 0u) | (P >= 8 ? 0xffff0000u : 0u);
+                rx_run_planes_first(rx_ring + (int)(P & 1) * RX_SLOT_WORDS, lane, s, acc, seen, vmask, P * 4,
+                                    (P - 8) * 4, base, n, first);
+            } else {
+                rx_run_planes(rx_ring + (int)(P & 1) * RX_SLOT_WORDS, lane, s, acc);
+            }
             if (P == ngroups - 1) acc_first = acc;
         }
         __syncthreads();
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // loads past the last matched half have landed
-    if (wave == 0) rx_store_result(out, base, n, lane, (acc_first & 0x0000ffffu) | (acc & 0xffff0000u));
+    if (wave != 0) return;
+    if (!FIRST) {
+        rx_store_result(out, base, n, lane, (acc_first & 0x0000ffffu) | (acc & 0xffff0000u));
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {   // strings whose accept never appeared
+        const long long sid = base + j * 64 + lane;
+        if (sid < n && !((seen >> j) & 1u)) first[sid] = -1;
+    }
 }
 
 extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_skew(const unsigned char* __restrict__ bytes,
         long long length, long long n, unsigned char* __restrict__ out) {
     extern __shared__ u32 rx_tile[];   // 32-byte tile of every string, then the ring
-    rx_skew<true>(bytes, length, n, out, rx_tile);
+    rx_skew<true, false>(bytes, length, n, out, nullptr, rx_tile);
 }
 
 extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_skew_w(const unsigned char* __restrict__ bytes,
         long long length, long long n, unsigned char* __restrict__ out) {
     extern __shared__ u32 rx_tile[];
-    rx_skew<false>(bytes, length, n, out, rx_tile);
+    rx_skew<false, false>(bytes, length, n, out, nullptr, rx_tile);
+}
+
+// Earliest accepting prefix of every string (the root is not nullable:
+// the caller answers 0 for every string otherwise).
+extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_first_skew(const unsigned char* __restrict__ bytes,
+        long long length, long long n, long long* __restrict__ first) {
+    extern __shared__ u32 rx_tile[];
+    rx_skew<true, true>(bytes, length, n, nullptr, first, rx_tile);
+}
+
+extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_first_skew_w(const unsigned char* __restrict__ bytes,
+        long long length, long long n, long long* __restrict__ first) {
+    extern __shared__ u32 rx_tile[];
+    rx_skew<false, true>(bytes, length, n, nullptr, first, rx_tile);
 }
 
 extern "C" __global__ __launch_bounds__(64, 1) void rx_sliced_fixed_pf(const unsigned char* __restrict__ bytes,
@@ -785,6 +856,8 @@ struct JitKernel {
     hipFunction_t split = nullptr;
     hipFunction_t skew = nullptr;
     bool skew_words = false;   // skew is the single-dword-read form
+    hipFunction_t first = nullptr;   // the skewed kernel's earliest-accept form
+    bool first_words = false;
     int dev = -1;
     int n_state = 0, n_ops = 0;
     std::string arch;
@@ -798,6 +871,15 @@ std::string jit_full_source(const Program& P, int* n_state, int* n_ops) {
     s << kFixedKernelSource;
     return s.str();
 }
+
+// Code objects by (architecture, source): a program whose circuit text was
+// compiled before in this process skips the device compiler.  Bounded; when
+// full it is emptied and refilled.
+namespace {
+std::mutex g_code_mu;
+std::unordered_map<std::string, std::vector<char>> g_code_cache;
+constexpr size_t kCodeCacheEntries = 64;
+}  // namespace
 
 int jit_compile(Program* P, const char* arch_in) {
     int ns = 0, nops = 0;
@@ -815,25 +897,37 @@ int jit_compile(Program* P, const char* arch_in) {
         if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(RX_EHIP, "hipGetDeviceProperties failed");
         arch = prop.gcnArchName;
     }
-    hiprtcProgram prog;
-    if (hiprtcCreateProgram(&prog, src.c_str(), "rx_sliced.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
-        return fail(RX_EJIT, "hiprtcCreateProgram failed");
-    const std::string arch_opt = "--gpu-architecture=" + arch;
-    const char* opts[] = {arch_opt.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
-    const hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
-    if (rc != HIPRTC_SUCCESS) {
-        size_t n = 0;
-        hiprtcGetProgramLogSize(prog, &n);
-        std::string log(n, '\0');
-        if (n) hiprtcGetProgramLog(prog, &log[0]);
-        hiprtcDestroyProgram(&prog);
-        return fail(RX_EJIT, "hiprtc compile failed: " + log.substr(0, 2000));
+    const std::string key = arch + '\n' + src;
+    std::vector<char> code;
+    {
+        std::lock_guard<std::mutex> lk(g_code_mu);
+        auto it = g_code_cache.find(key);
+        if (it != g_code_cache.end()) code = it->second;
     }
-    size_t code_size = 0;
-    hiprtcGetCodeSize(prog, &code_size);
-    std::vector<char> code(code_size);
-    hiprtcGetCode(prog, code.data());
-    hiprtcDestroyProgram(&prog);
+    if (code.empty()) {
+        hiprtcProgram prog;
+        if (hiprtcCreateProgram(&prog, src.c_str(), "rx_sliced.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+            return fail(RX_EJIT, "hiprtcCreateProgram failed");
+        const std::string arch_opt = "--gpu-architecture=" + arch;
+        const char* opts[] = {arch_opt.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+        const hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+        if (rc != HIPRTC_SUCCESS) {
+            size_t n = 0;
+            hiprtcGetProgramLogSize(prog, &n);
+            std::string log(n, '\0');
+            if (n) hiprtcGetProgramLog(prog, &log[0]);
+            hiprtcDestroyProgram(&prog);
+            return fail(RX_EJIT, "hiprtc compile failed: " + log.substr(0, 2000));
+        }
+        size_t code_size = 0;
+        hiprtcGetCodeSize(prog, &code_size);
+        code.resize(code_size);
+        hiprtcGetCode(prog, code.data());
+        hiprtcDestroyProgram(&prog);
+        std::lock_guard<std::mutex> lk(g_code_mu);
+        if (g_code_cache.size() >= kCodeCacheEntries) g_code_cache.clear();
+        g_code_cache.emplace(key, code);
+    }
     JitKernel* K = new JitKernel;
     K->arch = arch;
     K->n_state = ns;
@@ -845,9 +939,11 @@ int jit_compile(Program* P, const char* arch_in) {
         if (e == hipSuccess) e = hipModuleGetFunction(&K->fixed64, K->mod, "rx_sliced_fixed_pf");
         if (e == hipSuccess) e = hipModuleGetFunction(&K->duo, K->mod, "rx_sliced_fixed_duo");
         if (e == hipSuccess) e = hipModuleGetFunction(&K->split, K->mod, "rx_sliced_fixed_split");
-        hipFunction_t skew_w = nullptr;
+        hipFunction_t skew_w = nullptr, first_w = nullptr;
         if (e == hipSuccess) e = hipModuleGetFunction(&K->skew, K->mod, "rx_sliced_fixed_skew");
         if (e == hipSuccess) e = hipModuleGetFunction(&skew_w, K->mod, "rx_sliced_fixed_skew_w");
+        if (e == hipSuccess) e = hipModuleGetFunction(&K->first, K->mod, "rx_sliced_first_skew");
+        if (e == hipSuccess) e = hipModuleGetFunction(&first_w, K->mod, "rx_sliced_first_skew_w");
         if (e != hipSuccess) {
             hipModuleUnload(K->mod);
             delete K;
@@ -857,13 +953,15 @@ int jit_compile(Program* P, const char* arch_in) {
         // believes already hold their data; a kernel that spills could move
         // such a register before its load lands.  Those kernels are dropped
         // for this program and the LDS-staged kernel runs instead.
-        for (hipFunction_t* f : {&K->fixed64, &K->duo, &K->split, &K->skew, &skew_w}) {
+        for (hipFunction_t* f : {&K->fixed64, &K->duo, &K->split, &K->skew, &skew_w, &K->first, &first_w}) {
             int scratch = 1;
             if (hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, *f) != hipSuccess || scratch != 0)
                 *f = nullptr;
         }
         K->skew_words = !K->skew && skew_w;
         if (!K->skew) K->skew = skew_w;   // the skewed kernel with single-dword transposer reads
+        K->first_words = !K->first && first_w;
+        if (!K->first) K->first = first_w;
         K->dev = dev;
     }
     if (P->jit) jit_free(P);
@@ -892,8 +990,8 @@ int jit_default_staging(const Program* P) {
     return K->skew ? 5 : K->duo ? 3 : 2;
 }
 
-void jit_staging(const Program* P, int32_t staged[6]) {
-    for (int u = 0; u < 6; ++u) staged[u] = 0;
+void jit_staging(const Program* P, int32_t staged[7]) {
+    for (int u = 0; u < 7; ++u) staged[u] = 0;
     const JitKernel* K = static_cast<const JitKernel*>(P->jit);
     if (!K || !K->fixed) return;
     staged[0] = jit_default_staging(P);
@@ -902,6 +1000,26 @@ void jit_staging(const Program* P, int32_t staged[6]) {
     staged[3] = K->duo ? 1 : 0;
     staged[4] = K->split ? 1 : 0;
     staged[5] = K->skew ? (K->skew_words ? 2 : 1) : 0;
+    staged[6] = K->first ? (K->first_words ? 2 : 1) : 0;
+}
+
+bool jit_first_ready(const Program* P) {
+    const JitKernel* K = static_cast<const JitKernel*>(P->jit);
+    return K && K->first;
+}
+
+int launch_sliced_first(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, int64_t* first,
+                        void* stream) {
+    const JitKernel* K = static_cast<const JitKernel*>(P->jit);
+    if (!K || !K->first || length > (1 << 26)) return (int)hipErrorInvalidValue;
+    const long long grid = (n + 2047) / 2048;
+    const unsigned lds = 2048 * 32 + 2 * 2048 * 4;
+    long long len = length, nn = n;
+    const void* b = bytes;
+    void* f = first;
+    void* args[] = {&b, &len, &nn, &f};
+    return (int)hipModuleLaunchKernel(K->first, (unsigned)grid, 1, 1, 128, 1, 1, lds, (hipStream_t)stream, args,
+                                      nullptr);
 }
 
 int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,

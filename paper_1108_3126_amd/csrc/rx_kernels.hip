@@ -323,6 +323,18 @@ int launch_stream_copy(void* dst, const void* src, int64_t bytes, void* stream) 
     return (int)hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+int launch_fill_i64(int64_t* p, int64_t n, int64_t v, void* stream) {
+    int64_t grid = (n + 255) / 256;
+    if (grid > 4096) grid = 4096;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, p, n, v);
+    return (int)hipGetLastError();
+}
+
 const char* hip_error_string(int err) { return hipGetErrorString((hipError_t)err); }
 
 int hip_current_device(int* dev) { return (int)hipGetDevice(dev); }

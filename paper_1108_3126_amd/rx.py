@@ -99,6 +99,7 @@ SIGNATURES = {
     "rx_program_jit_stats": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "rx_program_jit_staging": (ctypes.c_int, [_VP, ctypes.POINTER(_I32)]),
     "rx_match_first": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _VP]),
+    "rx_match_first_fixed": (ctypes.c_int, [_VP, _VP, _I64, _I64, _VP, _VP]),
     "rx_parse": (ctypes.c_int, [ctypes.c_char_p, _SZ, _VP, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _VP, _I32,
                                 ctypes.POINTER(_I32)]),
     "rx_match_multi_workspace": (ctypes.c_int64, [_I64, _I32, ctypes.POINTER(rx_multi_config)]),
@@ -245,8 +246,8 @@ class Program:
         return {"ready": r.value, "state_words": s.value, "ops": o.value}
 
     def jit_staging(self):
-        """[default mode, then 1/0 for staging modes 1..5]: which sliced kernels run as themselves."""
-        st = (ctypes.c_int32 * 6)()
+        """[default mode, 1/0 for staging modes 1..5, earliest-accept form]: which sliced kernels run."""
+        st = (ctypes.c_int32 * 7)()
         _check(lib().rx_program_jit_staging(self._h, st))
         return list(st)
 
@@ -335,6 +336,24 @@ def match_first(prog: Program, data, offsets, out=None, stream=None):
     dptr = ctypes.c_void_p(data.data_ptr() if data.numel() else offsets.data_ptr())
     _check(lib().rx_match_first(prog.handle, dptr, ctypes.c_void_p(offsets.data_ptr()), n,
                                 ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def match_first_fixed(prog: Program, data, length: int, n: int = None, out=None, stream=None):
+    """match_first for fixed-length strings (string i = data[i*length:(i+1)*length])."""
+    import torch
+
+    if prog._dev_buf is None:
+        prog.upload(device=data.device, stream=stream)
+    if data.dtype != torch.uint8 or not data.is_cuda:
+        raise TypeError("data must be a uint8 device tensor")
+    data = data.contiguous()
+    if n is None:
+        n = data.numel() // length if length else 0
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.int64, device=data.device)
+    _check(lib().rx_match_first_fixed(prog.handle, ctypes.c_void_p(data.data_ptr()), int(length), int(n),
+                                      ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
 
 

@@ -43,6 +43,20 @@ def test_single_program_1m_x_256(dev):
     out2 = rx.match_fixed(p, d, 256, s.n, launch=(rx.VARIANT_LANE, 0, 0, 0))
     torch.cuda.synchronize()
     assert np.array_equal(out2.cpu().numpy(), got)
+    # earliest accepting prefix, sliced form: accepted iff the bit is set; a sample on every prefix
+    first = rx.match_first_fixed(p, d, 256, s.n)
+    torch.cuda.synchronize()
+    first = first.cpu().numpy()
+    assert np.array_equal((first >= 0).astype(np.uint8), got) and first.max() <= 256
+    sub = np.unique(np.concatenate([idx[::40], planted[:20], [s.n - 1]]))
+    pre = []
+    for i in sub:
+        w = bytes(s.data[i * 256:(i + 1) * 256])
+        pre += [w[:k] for k in range(257)]
+    ps = W.pack(pre)
+    acc = oracle.match(prog.ast, prog.root, prog.classes, True, ps.data, ps.offsets).reshape(len(sub), 257)
+    want_first = np.where(acc.any(axis=1), acc.argmax(axis=1), -1)
+    assert np.array_equal(first[sub], want_first)
 
 
 def test_multi_16_programs_4m_lines(dev):

@@ -201,9 +201,9 @@ def test_sliced_lengths_and_counts(dev, length, burst):
 
     rng = np.random.default_rng(length)
     prog = W.single_program(3)
+    p = rx.compile(prog.ast, prog.root, prog.classes, True).upload(dev).jit()
     for n in (1, 31, 33, 2047, 2049, 4100):
         s, _ = W.single_strings(prog, seed=length + n, n=n, length=length, plant_frac=0.3)
-        p = rx.compile(prog.ast, prog.root, prog.classes, True).upload(dev).jit()
         want = oracle_match(prog, s)
         assert np.array_equal(fixed_match(p, s, length, dev, rx.VARIANT_SLICED, burst), want), (length, n)
 
@@ -374,6 +374,102 @@ def test_match_first_wavefront_programs(dev):
         strings = [bytes(long.data[long.offsets[i]:long.offsets[i + 1]]) for i in range(long.n)]
         got = _gpu_first(p, strings, dev)
         assert (got[:32] == -1).all() and (got[32:] == 3000).all(), family
+
+
+def _gpu_first_fixed(p, s, length, dev, buf=None):
+    from paper_1108_3126_amd import rx
+
+    d = buf if buf is not None else torch.from_numpy(s.data if s.data.size else np.zeros(16, np.uint8)).to(dev)
+    out = rx.match_first_fixed(p, d, length, s.n)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_match_first_fixed_sliced_small_programs(dev):
+    """The skewed bit-sliced kernel's earliest-accept form: two-letter strings in three workgroups
+    (the last one ragged), every string against the oracle on every prefix."""
+    from paper_1108_3126_amd import rx
+
+    sliced = 0
+    for seed in range(12):
+        rng = np.random.default_rng(seed)
+        prog = W.small_program(300 + seed)
+        length = (16, 32, 48)[seed % 3]
+        n = 4096 + 37 * seed + 1
+        data = np.frombuffer(b"ab", np.uint8)[rng.integers(0, 2, size=n * length)].astype(np.uint8)
+        s = W.Strings(data, np.arange(n + 1, dtype=np.int64) * length)
+        strings = [bytes(data[i * length:(i + 1) * length]) for i in range(n)]
+        for search in (False, True):
+            prog.search = search
+            p = rx.compile(prog.ast, prog.root, prog.classes, search).upload(dev).jit()
+            assert p.jit_staging()[6] in (1, 2)
+            sliced += not p.info.nullable
+            want = _first_by_prefixes(prog, strings, search)
+            got = _gpu_first_fixed(p, s, length, dev)
+            assert np.array_equal(got, want), (seed, search, np.nonzero(got != want)[0][:5])
+    assert sliced >= 8
+
+
+def test_match_first_fixed_single_program(dev):
+    """~200-node searched expression, 256-byte strings: the sliced form against the table form on every
+    string, a sample against the oracle on every prefix, and accepted iff rx_match_fixed says so."""
+    from paper_1108_3126_amd import rx
+
+    prog = W.single_program(1)
+    s, planted = W.single_strings(prog, seed=34, n=6000, length=256, plant_frac=0.3)
+    p = rx.compile(prog.ast, prog.root, prog.classes, True).upload(dev).jit()
+    st = p.jit_staging()
+    print("first fixed: staging", st, flush=True)
+    assert st[6] == 1
+    got = _gpu_first_fixed(p, s, 256, dev)
+    table = _gpu_first(p, [bytes(s.data[i * 256:(i + 1) * 256]) for i in range(s.n)], dev)
+    assert np.array_equal(got, table)
+    assert (got[planted] > 0).all() and (got <= 256).all()
+    assert np.array_equal((got >= 0).astype(np.uint8), fixed_match(p, s, 256, dev))
+    idx = np.unique(np.concatenate([np.arange(0, s.n, 500), planted[:40], [2047, 2048, s.n - 1]]))
+    strings = [bytes(s.data[i * 256:(i + 1) * 256]) for i in idx]
+    assert np.array_equal(got[idx], _first_by_prefixes(prog, strings, True))
+
+
+def test_match_first_fixed_fallbacks(dev):
+    """Where the sliced kernel does not apply (length not a multiple of 16, unaligned bytes, no compiled
+    circuit, length 0) the table form answers; a nullable expression answers 0 for every string."""
+    from paper_1108_3126_amd import rx
+
+    prog = W.small_program(305)
+    rng = np.random.default_rng(3)
+    for length in (0, 7, 40):
+        n = 700
+        data = np.frombuffer(b"ab", np.uint8)[rng.integers(0, 2, size=n * length)].astype(np.uint8)
+        s = W.Strings(data, np.arange(n + 1, dtype=np.int64) * length)
+        strings = [bytes(data[i * length:(i + 1) * length]) for i in range(n)]
+        for search in (False, True):
+            prog.search = search
+            p = rx.compile(prog.ast, prog.root, prog.classes, search).upload(dev).jit()
+            assert np.array_equal(_gpu_first_fixed(p, s, length, dev), _first_by_prefixes(prog, strings, search))
+    # 64-byte strings one byte into the buffer, and the same strings with no compiled circuit
+    big = W.single_program(4)
+    s, _ = W.single_strings(big, seed=8, n=2100, length=64, plant_frac=0.4)
+    strings = [bytes(s.data[i * 64:(i + 1) * 64]) for i in range(s.n)]
+    want = _first_by_prefixes(big, strings, True)
+    p = rx.compile(big.ast, big.root, big.classes, True).upload(dev).jit()
+    buf = torch.zeros(s.data.size + 16, dtype=torch.uint8, device=dev)
+    buf[1:1 + s.data.size] = torch.from_numpy(s.data).to(dev)
+    assert np.array_equal(_gpu_first_fixed(p, s, 64, dev, buf=buf[1:1 + s.data.size]), want)
+    assert np.array_equal(_gpu_first_fixed(p, s, 64, dev), want)
+    q = rx.compile(big.ast, big.root, big.classes, True).upload(dev)
+    assert np.array_equal(_gpu_first_fixed(q, s, 64, dev), want)
+    # a nullable expression: the empty prefix is accepted
+    star = rx.compile_regex(b"(ab)*", search=False).upload(dev).jit()
+    assert star.info.nullable
+    assert (_gpu_first_fixed(star, s, 64, dev) == 0).all()
+    # long strings: nested stars, closed form a^n rejected, a^(n-1) t accepted at its end
+    for family, k in (("nested", 40), ("altstar", 30)):
+        pp = W.pathological_program(family, k)
+        ls = W.pathological_strings(family, 1008, count=64)
+        r = rx.compile(pp.ast, pp.root).upload(dev).jit()
+        got = _gpu_first_fixed(r, ls, 1008, dev)
+        assert (got[:32] == -1).all() and (got[32:] == 1008).all(), family
 
 
 def test_match_first_parsed_patterns_against_re(dev):

@@ -6,6 +6,7 @@ import ctypes
 import os
 import subprocess
 import tempfile
+import time
 
 import numpy as np
 import pytest
@@ -143,4 +144,8 @@ def test_hiprtc_compiles_for_gfx950():
     st = p.jit_stats()
     assert st["ready"] == 0 and st["state_words"] > 0 and st["ops"] > 0
     # nothing is loaded without a device: no staging mode is available yet
-    assert p.jit_staging() == [0, 0, 0, 0, 0, 0]
+    assert p.jit_staging() == [0] * 7
+    # the same circuit text again reuses the code object compiled above
+    t0 = time.perf_counter()
+    rx.compile(prog.ast, prog.root, prog.classes, True).jit("gfx950")
+    assert time.perf_counter() - t0 < 0.5
