@@ -245,6 +245,31 @@ int rx_match_first(const rx_program* prog, const uint8_t* d_bytes, const int64_t
 int rx_match_first_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int64_t n,
                          int64_t* d_first, void* stream);
 
+/* The paper's own GPU machine (§8, on the process translation of §7): every
+ * node of d[] is a process owned by one thread of a workgroup; stamp vectors
+ * c and n (in LDS) hold which processes have a message in the current macro
+ * step and which leaves moved on the byte; rounds of simulation run until
+ * none sends a new message, then c and n swap.  One persistent launch, one
+ * workgroup per string, barriers inside the kernel; the same results as
+ * rx_match (the lockstep machine it realises), without the precomputed
+ * evolution tables.  Kept for comparison: its rounds per byte grow with the
+ * longest chain of messages, not with the input.
+ *
+ * rx_program_node_image writes the device image this machine reads: 16
+ * bytes of header (m, number of classes), 16 bytes per node of d[] (kind |
+ * label << 8, c0, c1, cont) and 32 bytes per class.  *len = its size; buf may
+ * be NULL to query it; a buffer below *len gives RX_EINVAL.  The caller copies
+ * it to device memory it owns and passes it as d_image, unchanged, for this
+ * program only.
+ * Errors: RX_EINVAL (NULL arguments, short buffer). */
+int rx_program_node_image(const rx_program* prog, void* buf, size_t cap, size_t* len);
+
+/* Strings as in rx_match; asynchronous on stream.
+ * Errors: RX_EINVAL (NULL buffers, n < 0), RX_ETOOBIG (more than 8191 nodes:
+ * two 8-byte stamps per node in LDS), RX_EHIP. */
+int rx_match_nodes(const rx_program* prog, const void* d_image, const uint8_t* d_bytes, const int64_t* d_offsets,
+                   int64_t n, uint8_t* d_out, void* stream);
+
 /* rx_match with an explicit kernel variant and launch shape (the autotuner's
  * entry point).  Every variant returns the same bits (Thm. 7.2: the parallel
  * schedule does not change the result). */

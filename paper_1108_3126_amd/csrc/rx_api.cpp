@@ -197,6 +197,39 @@ int rx_match(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_of
     return rx_match_ex(prog, d_bytes, d_offsets, n, d_out, nullptr, stream);
 }
 
+int rx_program_node_image(const rx_program* prog, void* buf, size_t cap, size_t* len) {
+    RX_GUARD_BEGIN
+    const Program* P = reinterpret_cast<const Program*>(prog);
+    if (!P || !len) return fail(RX_EINVAL, "NULL argument");
+    std::vector<uint8_t> img;
+    node_image(P, img);
+    *len = img.size();
+    if (buf) {
+        if (cap < img.size())
+            return fail(RX_EINVAL, "node image needs " + std::to_string(img.size()) + " bytes, buffer holds " +
+                                       std::to_string(cap));
+        std::memcpy(buf, img.data(), img.size());
+    }
+    return RX_OK;
+    RX_GUARD_END
+}
+
+int rx_match_nodes(const rx_program* prog, const void* d_image, const uint8_t* d_bytes, const int64_t* d_offsets,
+                   int64_t n, uint8_t* d_out, void* stream) {
+    RX_GUARD_BEGIN
+    const Program* P = reinterpret_cast<const Program*>(prog);
+    if (!P) return fail(RX_EINVAL, "program is NULL");
+    if (n < 0) return fail(RX_EINVAL, "negative string count");
+    if (n == 0) return RX_OK;
+    if (!d_image || !d_bytes || !d_offsets || !d_out) return fail(RX_EINVAL, "NULL device buffer");
+    if (P->m > kNodesMaxNodes)
+        return fail(RX_ETOOBIG, "the node-per-thread machine keeps stamps for at most " +
+                                    std::to_string(kNodesMaxNodes) + " nodes; this program has " + std::to_string(P->m));
+    if (int e = launch_nodes(d_image, P->m, d_bytes, d_offsets, 0, n, d_out, stream)) return hip_fail(e, "kernel launch");
+    return RX_OK;
+    RX_GUARD_END
+}
+
 int rx_match_first_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int64_t n,
                          int64_t* d_first, void* stream) {
     RX_GUARD_BEGIN

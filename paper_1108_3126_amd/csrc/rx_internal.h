@@ -16,6 +16,7 @@ constexpr int kMaxNodes = 1 << 20;
 constexpr int kLaneMaxWords = 16;       // one-lane-per-string kernel limit (L <= 511)
 constexpr int kWaveMaxWords = 128;      // wavefront kernel limit: lane j owns words j and j+64
 constexpr int kJitMaxState = 160;       // sliced circuit: leaf state words kept in registers
+constexpr int kNodesMaxNodes = 8191;    // node-per-thread machine: two stamp vectors of m + 1 in LDS
 
 // Device table layout (all offsets in bytes from the start of the uploaded
 // buffer, each section 256-byte aligned).
@@ -162,6 +163,10 @@ int jit_default_staging(const Program* P);
 bool jit_first_ready(const Program* P);
 int launch_sliced_first(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, int64_t* first,
                         void* stream);
+// The node-per-thread machine (rx_nodes.hip): host image of d[] and its launch.
+void node_image(const Program* P, std::vector<uint8_t>& img);
+int launch_nodes(const void* image, int32_t m, const uint8_t* bytes, const int64_t* offsets, int64_t stride, int64_t n,
+                 uint8_t* out, void* stream);
 // first[i] = value for i < n (a fill kernel, no memset)
 int launch_fill_i64(int64_t* first, int64_t n, int64_t value, void* stream);
 int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,

@@ -100,6 +100,8 @@ SIGNATURES = {
     "rx_program_jit_staging": (ctypes.c_int, [_VP, ctypes.POINTER(_I32)]),
     "rx_match_first": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _VP]),
     "rx_match_first_fixed": (ctypes.c_int, [_VP, _VP, _I64, _I64, _VP, _VP]),
+    "rx_program_node_image": (ctypes.c_int, [_VP, _VP, _SZ, ctypes.POINTER(_SZ)]),
+    "rx_match_nodes": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I64, _VP, _VP]),
     "rx_parse": (ctypes.c_int, [ctypes.c_char_p, _SZ, _VP, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _VP, _I32,
                                 ctypes.POINTER(_I32)]),
     "rx_match_multi_workspace": (ctypes.c_int64, [_I64, _I32, ctypes.POINTER(rx_multi_config)]),
@@ -245,6 +247,14 @@ class Program:
         _check(lib().rx_program_jit_stats(self._h, ctypes.byref(r), ctypes.byref(s), ctypes.byref(o)))
         return {"ready": r.value, "state_words": s.value, "ops": o.value}
 
+    def node_image(self) -> bytes:
+        """Device image of d[] for the node-per-thread machine (header, 16 bytes per node, classes)."""
+        n = _SZ()
+        _check(lib().rx_program_node_image(self._h, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib().rx_program_node_image(self._h, buf, n.value, ctypes.byref(n)))
+        return buf.raw[: n.value]
+
     def jit_staging(self):
         """[default mode, 1/0 for staging modes 1..5, earliest-accept form]: which sliced kernels run."""
         st = (ctypes.c_int32 * 7)()
@@ -336,6 +346,30 @@ def match_first(prog: Program, data, offsets, out=None, stream=None):
     dptr = ctypes.c_void_p(data.data_ptr() if data.numel() else offsets.data_ptr())
     _check(lib().rx_match_first(prog.handle, dptr, ctypes.c_void_p(offsets.data_ptr()), n,
                                 ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def match_nodes(prog: Program, data, offsets, out=None, stream=None):
+    """The node-per-thread machine (one thread per node of d[], stamp vectors c and n): uint8 0/1 per string."""
+    import torch
+
+    if data.dtype != torch.uint8 or offsets.dtype != torch.int64:
+        raise TypeError("data must be uint8 and offsets int64")
+    if not (data.is_cuda and offsets.is_cuda):
+        raise TypeError("data and offsets must be device tensors")
+    img = getattr(prog, "_node_dev", None)
+    if img is None or img.device != offsets.device:
+        host = prog.node_image()
+        img = torch.frombuffer(bytearray(host), dtype=torch.uint8).to(offsets.device)
+        prog._node_dev = img
+    data = data.contiguous()
+    offsets = offsets.contiguous()
+    n = offsets.numel() - 1
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.uint8, device=offsets.device)
+    dptr = ctypes.c_void_p(data.data_ptr() if data.numel() else offsets.data_ptr())
+    _check(lib().rx_match_nodes(prog.handle, ctypes.c_void_p(img.data_ptr()), dptr, ctypes.c_void_p(offsets.data_ptr()),
+                                n, ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
 
 
