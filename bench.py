@@ -271,10 +271,24 @@ def run_small(args, torch, dev):
         e.record()
     torch.cuda.synchronize()
     us = sorted(a.elapsed_time(e) * 1e3 for a, e in ev)
-    ok = bool(np.array_equal(out.cpu().numpy(), oracle.match(prog.ast, prog.root, prog.classes, False, s.data,
-                                                           s.offsets)))
+    want = oracle.match(prog.ast, prog.root, prog.classes, False, s.data, s.offsets)
+    ok = bool(np.array_equal(out.cpu().numpy(), want))
+    # the paper's node-per-thread machine on the same batch
+    nout = torch.empty(s.n, dtype=torch.uint8, device=dev)
+    for _ in range(20):
+        rx.match_nodes(p, d, o, out=nout)
+    torch.cuda.synchronize()
+    for a, e in ev:
+        a.record()
+        rx.match_nodes(p, d, o, out=nout)
+        e.record()
+    torch.cuda.synchronize()
+    nus = sorted(a.elapsed_time(e) * 1e3 for a, e in ev)
+    nok = bool(np.array_equal(nout.cpu().numpy(), want))
     return {"metric": "us per call", "workload": "small: 1 expression over {a,b}, 1,000 strings of length 0..32",
-            "median_us": round(us[len(us) // 2], 2), "p99_us": round(us[int(len(us) * 0.99)], 2), "bit_exact": ok}
+            "median_us": round(us[len(us) // 2], 2), "p99_us": round(us[int(len(us) * 0.99)], 2), "bit_exact": ok,
+            "node_machine": {"median_us": round(nus[len(nus) // 2], 2), "p99_us": round(nus[int(len(nus) * 0.99)], 2),
+                             "bit_exact": nok}}
 
 
 def run_multi(args, torch, dev):
@@ -365,6 +379,25 @@ def run_pathological(args, torch, dev):
                               "closed_form_ok": bool(got[:128].sum() == 0 and got[128:].all())}
         fam["k_scaling_n1e4"] = scale
         log(f"pathological {family} k scaling at n=1e4: {scale}")
+        # the paper's node-per-thread machine (one workgroup per string, one thread per node)
+        nm = {}
+        for n_len in (1000, 10000):
+            s = W.pathological_strings(family, n_len, count=256)
+            d, o = torch.from_numpy(s.data).to(dev), torch.from_numpy(s.offsets).to(dev)
+            out = rx.match_nodes(p, d, o)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rx.match_nodes(p, d, o, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            nm[str(n_len)] = {"ms": round(e0.elapsed_time(e1), 3),
+                              "closed_form_ok": bool(got[:128].sum() == 0 and got[128:].all())}
+            log(f"pathological {family} node machine n={n_len}: {nm[str(n_len)]}")
+            if nm[str(n_len)]["ms"] > 2000:
+                break
+        fam["node_machine"] = nm
         res["families"][family] = fam
     return res
 
