@@ -245,6 +245,25 @@ int rx_match_first(const rx_program* prog, const uint8_t* d_bytes, const int64_t
 int rx_match_first_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int64_t n,
                          int64_t* d_first, void* stream);
 
+/* Chunk-parallel matching of one long string d_bytes[0, length): the result
+ * bit (1 byte) goes to d_out[0].  The byte step of the lockstep machine maps a
+ * union of thread sets to the union of their images (§5, Def. 5.1 / 5.2: a
+ * set evolves pointer by pointer), so a chunk of the input acts on sets as a
+ * relation: T[r] = the set reached from leaf r alone.  A first launch runs,
+ * in parallel, chunk 0 from First and every later chunk from every single
+ * leaf (and from the accept bit alone), one lane per run for sets of at most
+ * 16 words, one wavefront above; a second launch applies the relations in
+ * order.  Work grows by the number of leaves, time falls by the number of
+ * chunks: for strings far longer than the expression.
+ * chunks: 0 = about sqrt(length / 20), else the count wanted (at most 4096
+ * and at most length are used).  d_work: caller-owned device memory of at
+ * least rx_match_long_workspace bytes (the rows, u32 words).
+ * Errors: RX_EINVAL (NULL buffers, negative sizes, short workspace),
+ * RX_ENOTUPLOADED, RX_ETOOBIG (sets above 128 words), RX_EHIP. */
+int rx_match_long_workspace(const rx_program* prog, int64_t length, int32_t chunks, size_t* bytes);
+int rx_match_long(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int32_t chunks, void* d_work,
+                  size_t work_bytes, uint8_t* d_out, void* stream);
+
 /* The paper's own GPU machine (§8, on the process translation of §7): every
  * node of d[] is a process owned by one thread of a workgroup; stamp vectors
  * c and n (in LDS) hold which processes have a message in the current macro

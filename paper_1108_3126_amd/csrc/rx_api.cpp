@@ -1,6 +1,7 @@
 // C interface of the lockstep matcher: program lifetime, upload and launch
 // selection.  Every entry point catches everything and reports through a
 // thread-local message.
+#include <cmath>
 #include <cstring>
 #include <exception>
 #include <string>
@@ -195,6 +196,70 @@ int rx_match_ex(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d
 int rx_match(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t n,
              uint8_t* d_out, void* stream) {
     return rx_match_ex(prog, d_bytes, d_offsets, n, d_out, nullptr, stream);
+}
+
+namespace {
+// Chunks of a chunk-parallel run: the requested count (0: about sqrt(length / 20),
+// which balances the rows' length against the composition's per-chunk cost),
+// at most 4096 and at most one per byte; every chunk holds at least one byte.
+void long_chunks(int64_t length, int32_t chunks, int64_t* C, int64_t* cl) {
+    int64_t c = chunks > 0 ? chunks : (int64_t)std::llround(std::sqrt((double)length / 20.0));
+    if (c > 4096) c = 4096;
+    if (c > length) c = length;
+    if (c < 1) c = 1;
+    *cl = length > 0 ? (length + c - 1) / c : 0;
+    *C = length > 0 ? (length + *cl - 1) / *cl : 1;
+}
+
+size_t long_rows_bytes(const Program* P, int64_t C) {
+    return (size_t)(1 + (C - 1) * (int64_t)(P->L + 1)) * (size_t)P->W * 4;
+}
+}  // namespace
+
+int rx_match_long_workspace(const rx_program* prog, int64_t length, int32_t chunks, size_t* bytes) {
+    RX_GUARD_BEGIN
+    const Program* P = reinterpret_cast<const Program*>(prog);
+    if (!P || !bytes) return fail(RX_EINVAL, "NULL argument");
+    if (length < 0 || chunks < 0) return fail(RX_EINVAL, "negative length or chunk count");
+    int64_t C, cl;
+    long_chunks(length, chunks, &C, &cl);
+    *bytes = long_rows_bytes(P, C);
+    return RX_OK;
+    RX_GUARD_END
+}
+
+int rx_match_long(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int32_t chunks, void* d_work,
+                  size_t work_bytes, uint8_t* d_out, void* stream) {
+    RX_GUARD_BEGIN
+    const Program* P = reinterpret_cast<const Program*>(prog);
+    if (!P) return fail(RX_EINVAL, "program is NULL");
+    if (length < 0 || chunks < 0) return fail(RX_EINVAL, "negative length or chunk count");
+    if (!d_out || !d_work || (length > 0 && !d_bytes)) return fail(RX_EINVAL, "NULL device buffer");
+    if (!P->dev) return fail(RX_ENOTUPLOADED, "program has not been uploaded (rx_program_upload)");
+    if (P->W > kWaveMaxWords) return fail(RX_ETOOBIG, "the wavefront kernel holds sets of at most 128 words");
+    int64_t C, cl;
+    long_chunks(length, chunks, &C, &cl);
+    const size_t need = long_rows_bytes(P, C);
+    if (work_bytes < need)
+        return fail(RX_EINVAL, "workspace holds " + std::to_string(work_bytes) + " bytes; this run needs " +
+                                   std::to_string(need) + " (rx_match_long_workspace)");
+    LaunchArgs a;
+    const int64_t rows = 1 + (C - 1) * (int64_t)(P->L + 1);
+    if (int rc = make_launch_args(P, d_bytes ? d_bytes : static_cast<const uint8_t*>(d_work),
+                                  static_cast<const int64_t*>(d_work), rows, d_out, stream, &a))
+        return rc;
+    a.offsets = nullptr;
+    a.out = nullptr;
+    a.rows_out = static_cast<uint32_t*>(d_work);
+    a.rows_len = length;
+    a.rows_cl = cl;
+    a.rows_per_chunk = P->L + 1;
+    int e = P->W <= kLaneMaxWords ? launch_lane(a) : launch_wave(a);
+    if (e) return hip_fail(e, "kernel launch (rows)");
+    e = launch_compose(a.rows_out, C, P->L + 1, P->W, P->L, P->suffix_any ? 1 : 0, d_out, stream);
+    if (e) return hip_fail(e, "kernel launch (composition)");
+    return RX_OK;
+    RX_GUARD_END
 }
 
 int rx_program_node_image(const rx_program* prog, void* buf, size_t cap, size_t* len) {

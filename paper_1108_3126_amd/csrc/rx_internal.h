@@ -147,6 +147,10 @@ struct LaunchArgs {
     int32_t block, grid, unroll;
     void* stream;
     int64_t* first_pos = nullptr;   // rx_match_first: earliest accepting prefix per string (out unused)
+    // rx_match_long, first pass: n rows of a chunk-parallel run (see KArgs in rx_kernels.hip)
+    uint32_t* rows_out = nullptr;
+    int64_t rows_len = 0, rows_cl = 0;
+    int32_t rows_per_chunk = 0;
 };
 int launch_lane(const LaunchArgs& a);
 // bit-sliced node circuit (rx_jit.cpp)
@@ -172,6 +176,9 @@ int launch_fill_i64(int64_t* first, int64_t n, int64_t value, void* stream);
 int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,
                         int burst, void* stream);
 int launch_wave(const LaunchArgs& a);
+// rx_match_long, second pass: one workgroup applies the chunks' relations in order
+int launch_compose(const uint32_t* rows, int64_t chunks, int32_t rpc, int32_t W, int32_t L, int32_t suffix_any,
+                   uint8_t* out, void* stream);
 const char* hip_error_string(int err);
 int launch_stream_copy(void* dst, const void* src, int64_t bytes, void* stream);
 int hip_current_device(int* dev);

@@ -40,7 +40,26 @@ struct KArgs {
     int64_t n;
     uint8_t* out;
     int64_t* first_pos;   // FIRST kernels: the earliest accepting prefix length, -1 if none
+    // ROWS kernels (chunk-parallel matching of one string bytes[0, rows_len)):
+    // row 0 runs chunk 0 from First; row 1 + (c - 1) * rows_per_chunk + r
+    // runs chunk c (bytes [c * rows_cl, (c + 1) * rows_cl)) from the set {r}
+    // (r = L: the accept bit alone); each writes its final set to rows_out.
+    uint32_t* rows_out;
+    int64_t rows_len, rows_cl;
+    int32_t rows_per_chunk, rows_pad;
 };
+
+// Start and byte range of row j of the chunk-parallel run.
+__device__ __forceinline__ void row_span(const KArgs& a, int64_t j, int* r, int64_t* lo, int64_t* hi) {
+    int64_t c = 0;
+    *r = -1;
+    if (j > 0) {
+        c = 1 + (j - 1) / a.rows_per_chunk;
+        *r = (int)((j - 1) % a.rows_per_chunk);
+    }
+    *lo = c * a.rows_cl;
+    *hi = *lo + a.rows_cl < a.rows_len ? *lo + a.rows_cl : a.rows_len;
+}
 
 template <int W>
 __device__ __forceinline__ uint32_t pick(const uint32_t (&S)[W], int w) {
@@ -84,7 +103,7 @@ __device__ __forceinline__ void lane_step(uint32_t (&S)[W], uint32_t c, const ui
 
 // FIRST: instead of the result bit, the smallest k such that the accept bit
 // is in S after the first k bytes (k = 0: the root is nullable), or -1.
-template <int W, bool FIRST>
+template <int W, bool FIRST, bool ROWS>
 __global__ __launch_bounds__(256) void k_lane(KArgs a) {
     extern __shared__ uint32_t lds[];
     uint32_t* M = lds;
@@ -97,10 +116,18 @@ __global__ __launch_bounds__(256) void k_lane(KArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t sid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; sid < a.n; sid += stride) {
         uint32_t S[W];
+        int64_t lo, hi;
+        if (ROWS) {
+            int r;
+            row_span(a, sid, &r, &lo, &hi);
 #pragma unroll
-        for (int w = 0; w < W; ++w) S[w] = a.first[w];
-        const int64_t lo = a.offsets ? a.offsets[sid] : sid * a.stride;
-        const int64_t hi = a.offsets ? a.offsets[sid + 1] : lo + a.stride;
+            for (int w = 0; w < W; ++w) S[w] = r < 0 ? a.first[w] : ((r >> 5) == w ? 1u << (r & 31) : 0u);
+        } else {
+#pragma unroll
+            for (int w = 0; w < W; ++w) S[w] = a.first[w];
+            lo = a.offsets ? a.offsets[sid] : sid * a.stride;
+            hi = a.offsets ? a.offsets[sid + 1] : lo + a.stride;
+        }
         int res = -1;
         int64_t pos = (FIRST && (pick<W>(S, aw) & abit)) ? 0 : -1;
         // aligned 16-byte blocks of the absolute address range [bytes+lo, bytes+hi):
@@ -124,6 +151,12 @@ __global__ __launch_bounds__(256) void k_lane(KArgs a) {
             if (any == 0) { res = 0; break; }                          // no live thread: reject
             if (!FIRST && a.suffix_any && (pick<W>(S, aw) & abit)) { res = 1; break; }  // accept is absorbing
         }
+        if (ROWS) {   // the set reached; an absorbed accept stands alone
+            uint32_t* o = a.rows_out + sid * W;
+#pragma unroll
+            for (int w = 0; w < W; ++w) o[w] = res == 1 ? (w == aw ? abit : 0u) : S[w];
+            continue;
+        }
         if (FIRST) {
             a.first_pos[sid] = pos;
             continue;
@@ -134,7 +167,7 @@ __global__ __launch_bounds__(256) void k_lane(KArgs a) {
 }
 
 // One wavefront per string.  Lane j owns words j and j + 64 of the set.
-template <bool TABLES_IN_LDS, bool FIRST>
+template <bool TABLES_IN_LDS, bool FIRST, bool ROWS>
 __global__ __launch_bounds__(1024) void k_wave(KArgs a) {
     extern __shared__ uint32_t lds[];
     const int W = a.W, L = a.L;
@@ -158,8 +191,18 @@ __global__ __launch_bounds__(1024) void k_wave(KArgs a) {
     for (int64_t sid = (int64_t)blockIdx.x * waves + wave; sid < a.n; sid += (int64_t)gridDim.x * waves) {
         uint32_t S0 = own0 ? a.first[lane] : 0u;
         uint32_t S1 = own1 ? a.first[lane + 64] : 0u;
-        const int64_t lo = a.offsets ? a.offsets[sid] : sid * a.stride;
-        const int64_t hi = a.offsets ? a.offsets[sid + 1] : lo + a.stride;
+        int64_t lo, hi;
+        if (ROWS) {
+            int r;
+            row_span(a, sid, &r, &lo, &hi);
+            if (r >= 0) {
+                S0 = (r >> 5) == lane ? 1u << (r & 31) : 0u;
+                S1 = (r >> 5) == lane + 64 ? 1u << (r & 31) : 0u;
+            }
+        } else {
+            lo = a.offsets ? a.offsets[sid] : sid * a.stride;
+            hi = a.offsets ? a.offsets[sid + 1] : lo + a.stride;
+        }
         int res = -1;
         int64_t pos = -1;
         if (FIRST) {
@@ -217,6 +260,12 @@ __global__ __launch_bounds__(1024) void k_wave(KArgs a) {
                 if (sw & abit) { res = 1; break; }
             }
         }
+        if (ROWS) {   // the set reached; an absorbed accept stands alone
+            uint32_t* o = a.rows_out + sid * W;
+            if (own0) o[lane] = res == 1 ? (lane == aw ? abit : 0u) : S0;
+            if (own1) o[lane + 64] = res == 1 ? (lane + 64 == aw ? abit : 0u) : S1;
+            continue;
+        }
         if (FIRST) {
             if (lane == 0) a.first_pos[sid] = pos;
             continue;
@@ -245,6 +294,11 @@ KArgs kargs(const LaunchArgs& a) {
     k.n = a.n;
     k.out = a.out;
     k.first_pos = a.first_pos;
+    k.rows_out = a.rows_out;
+    k.rows_len = a.rows_len;
+    k.rows_cl = a.rows_cl;
+    k.rows_per_chunk = a.rows_per_chunk;
+    k.rows_pad = 0;
     return k;
 }
 
@@ -255,10 +309,12 @@ int launch_lane_w(const LaunchArgs& a) {
     int grid = a.grid > 0 ? a.grid : (int)(need < (1 << 30) ? need : (1 << 30));
     if (grid < 1) grid = 1;
     const size_t lds = 4 * (size_t)(256 + a.L) * W;
-    if (a.first_pos)
-        hipLaunchKernelGGL((k_lane<W, true>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
+    if (a.rows_out)
+        hipLaunchKernelGGL((k_lane<W, false, true>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
+    else if (a.first_pos)
+        hipLaunchKernelGGL((k_lane<W, true, false>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
     else
-        hipLaunchKernelGGL((k_lane<W, false>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
+        hipLaunchKernelGGL((k_lane<W, false, false>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
     return (int)hipGetLastError();
 }
 
@@ -283,25 +339,66 @@ int launch_wave(const LaunchArgs& a) {
     int grid = a.grid > 0 ? a.grid : (int)(need < (1 << 30) ? need : (1 << 30));
     if (grid < 1) grid = 1;
     const size_t lds = 4 * (size_t)(256 + a.L) * a.W;
-    if (lds <= 150 * 1024) {
+    if (a.rows_out) {
+        // many independent rows: tables through the caches, so more waves fit per CU
+        hipLaunchKernelGGL((k_wave<false, false, true>), dim3(grid), dim3(block), 0, (hipStream_t)a.stream, kargs(a));
+    } else if (lds <= 150 * 1024) {
         static bool attr_set = false;
         if (!attr_set) {
-            hipFuncSetAttribute((const void*)k_wave<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+            hipFuncSetAttribute((const void*)k_wave<true, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 160 * 1024);
-            hipFuncSetAttribute((const void*)k_wave<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+            hipFuncSetAttribute((const void*)k_wave<true, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 160 * 1024);
             attr_set = true;
         }
         if (a.first_pos)
-            hipLaunchKernelGGL((k_wave<true, true>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
+            hipLaunchKernelGGL((k_wave<true, true, false>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
         else
-            hipLaunchKernelGGL((k_wave<true, false>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
+            hipLaunchKernelGGL((k_wave<true, false, false>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
     } else if (a.first_pos) {
-        hipLaunchKernelGGL((k_wave<false, true>), dim3(grid), dim3(block), 0, (hipStream_t)a.stream, kargs(a));
+        hipLaunchKernelGGL((k_wave<false, true, false>), dim3(grid), dim3(block), 0, (hipStream_t)a.stream, kargs(a));
     } else {
-        hipLaunchKernelGGL((k_wave<false, false>), dim3(grid), dim3(block), 0, (hipStream_t)a.stream, kargs(a));
+        hipLaunchKernelGGL((k_wave<false, false, false>), dim3(grid), dim3(block), 0, (hipStream_t)a.stream, kargs(a));
     }
     return (int)hipGetLastError();
+}
+
+// Chunk-parallel matching, second pass: apply the chunks' relations in order.
+// S starts as row 0 (chunk 0 run from First); for chunk c the new set is the
+// union of the rows T_c[r] over the leaves r in S, because the byte step maps
+// a union of thread sets to the union of their images (Def. 5.1 / 5.2: the
+// evolution of a set is the union of the evolutions of its pointers).  One
+// workgroup; exits early when S is empty or holds an absorbing accept.
+__global__ __launch_bounds__(1024) void k_compose(const uint32_t* __restrict__ T, int64_t chunks, int32_t rpc,
+                                                  int32_t W, int32_t L, int32_t suffix_any,
+                                                  uint8_t* __restrict__ out) {
+    __shared__ uint32_t S[kWaveMaxWords], N[kWaveMaxWords];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int aw = L >> 5;
+    const uint32_t abit = 1u << (L & 31);
+    for (int w = tid; w < W; w += nt) S[w] = T[w];
+    __syncthreads();
+    for (int64_t c = 1; c < chunks; ++c) {
+        uint32_t any = 0;
+        for (int w = 0; w < W; ++w) any |= S[w];
+        if (any == 0) break;                          // no live thread: reject
+        if (suffix_any && (S[aw] & abit)) break;      // accept is absorbing
+        for (int w = tid; w < W; w += nt) N[w] = 0;
+        __syncthreads();
+        const uint32_t* rows = T + (1 + (c - 1) * (int64_t)rpc) * W;
+        for (int r = tid; r < rpc; r += nt) {
+            if (!((S[r >> 5] >> (r & 31)) & 1u)) continue;
+            const uint32_t* row = rows + (int64_t)r * W;
+            for (int w = 0; w < W; ++w) {
+                const uint32_t v = row[w];
+                if (v) atomicOr(&N[w], v);
+            }
+        }
+        __syncthreads();
+        for (int w = tid; w < W; w += nt) S[w] = N[w];
+        __syncthreads();
+    }
+    if (tid == 0) out[0] = (S[aw] & abit) ? 1 : 0;
 }
 
 // Streaming copy (measurement only): the practical HBM ceiling and the
@@ -309,6 +406,15 @@ int launch_wave(const LaunchArgs& a) {
 __global__ __launch_bounds__(256) void k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
+}
+
+int launch_compose(const uint32_t* rows, int64_t chunks, int32_t rpc, int32_t W, int32_t L, int32_t suffix_any,
+                   uint8_t* out, void* stream) {
+    int threads = ((rpc + 63) / 64) * 64;
+    if (threads > 1024) threads = 1024;
+    hipLaunchKernelGGL(k_compose, dim3(1), dim3(threads), 0, (hipStream_t)stream, rows, chunks, rpc, W, L, suffix_any,
+                       out);
+    return (int)hipGetLastError();
 }
 
 int launch_stream_copy(void* dst, const void* src, int64_t bytes, void* stream) {

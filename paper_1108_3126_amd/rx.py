@@ -101,6 +101,8 @@ SIGNATURES = {
     "rx_match_first": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _VP]),
     "rx_match_first_fixed": (ctypes.c_int, [_VP, _VP, _I64, _I64, _VP, _VP]),
     "rx_program_node_image": (ctypes.c_int, [_VP, _VP, _SZ, ctypes.POINTER(_SZ)]),
+    "rx_match_long_workspace": (ctypes.c_int, [_VP, _I64, _I32, ctypes.POINTER(_SZ)]),
+    "rx_match_long": (ctypes.c_int, [_VP, _VP, _I64, _I32, _VP, _SZ, _VP, _VP]),
     "rx_match_nodes": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I64, _VP, _VP]),
     "rx_parse": (ctypes.c_int, [ctypes.c_char_p, _SZ, _VP, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _VP, _I32,
                                 ctypes.POINTER(_I32)]),
@@ -346,6 +348,28 @@ def match_first(prog: Program, data, offsets, out=None, stream=None):
     dptr = ctypes.c_void_p(data.data_ptr() if data.numel() else offsets.data_ptr())
     _check(lib().rx_match_first(prog.handle, dptr, ctypes.c_void_p(offsets.data_ptr()), n,
                                 ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def match_long(prog: Program, data, length: int = None, chunks: int = 0, out=None, stream=None):
+    """Chunk-parallel matching of one long string data[:length]: a 1-element uint8 tensor (0/1)."""
+    import torch
+
+    if prog._dev_buf is None:
+        prog.upload(device=data.device, stream=stream)
+    if data.dtype != torch.uint8 or not data.is_cuda:
+        raise TypeError("data must be a uint8 device tensor")
+    data = data.contiguous()
+    if length is None:
+        length = data.numel()
+    need = _SZ()
+    _check(lib().rx_match_long_workspace(prog.handle, int(length), int(chunks), ctypes.byref(need)))
+    work = torch.empty(max(int(need.value), 4), dtype=torch.uint8, device=data.device)
+    if out is None:
+        out = torch.empty(1, dtype=torch.uint8, device=data.device)
+    dptr = ctypes.c_void_p(data.data_ptr() if data.numel() else work.data_ptr())
+    _check(lib().rx_match_long(prog.handle, dptr, int(length), int(chunks), ctypes.c_void_p(work.data_ptr()),
+                               work.numel(), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
 
 
