@@ -82,7 +82,7 @@ def main():
     ap.add_argument("--serving", type=int, default=2000, help="requests per serving load point (0 = skip)")
     ap.add_argument("--copy-only", action="store_true", help="only run the stream-copy probe (counter calibration)")
     ap.add_argument("--serving-only", action="store_true", help="only run the serving comparison")
-    ap.add_argument("--workload", choices=["single", "small", "multi", "pathological"], default="single",
+    ap.add_argument("--workload", choices=["single", "small", "multi", "pathological", "long"], default="single",
                     help="single is the benchmark; the others measure the remaining configurations")
     ap.add_argument("--multi-lines", type=int, default=4_000_000)
     ap.add_argument("--copy-bytes", type=int, default=1 << 28)
@@ -107,7 +107,8 @@ def main():
         print(json.dumps(run_serving(args, torch)), flush=True)
         return
     if args.workload != "single":
-        fn = {"small": run_small, "multi": run_multi, "pathological": run_pathological}[args.workload]
+        fn = {"small": run_small, "multi": run_multi, "pathological": run_pathological,
+              "long": run_long}[args.workload]
         print(json.dumps(fn(args, torch, dev)), flush=True)
         return
     t0 = time.time()
@@ -399,6 +400,71 @@ def run_pathological(args, torch, dev):
                 break
         fam["node_machine"] = nm
         res["families"][family] = fam
+    return res
+
+
+def run_long(args, torch, dev):
+    """One long string: the lockstep run over the whole string (one lane or one wavefront) against the
+    chunk-parallel run (rx_match_long), for the ~200-node searched expression and the 4,096-node families."""
+    from paper_1108_3126_amd import rx
+    from paper_1108_3126_amd import workloads as W
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, int(r.cpu().numpy()[0])
+
+    res = {"metric": "ms per string", "workload": "long: one string", "cases": []}
+    prog = W.single_program(1)
+    p = rx.compile(prog.ast, prog.root, prog.classes, True).upload(dev)
+    # text with no match: a 256-byte piece that the expression rejects, also when doubled, repeated
+    pieces, _ = W.single_strings(prog, seed=30, n=4096, length=256, plant_frac=0.0)
+    pd = torch.from_numpy(pieces.data).to(dev)
+    bits = rx.match_fixed(p, pd, 256, pieces.n).cpu().numpy()
+    piece = None
+    for i in np.nonzero(bits == 0)[0][:64]:
+        w = pieces.data[i * 256:(i + 1) * 256]
+        two = torch.from_numpy(np.concatenate([w, w])).to(dev)
+        if int(rx.match_fixed(p, two, 512, 1).cpu().numpy()[0]) == 0:
+            piece = w
+            break
+    member, _ = W.single_strings(prog, seed=31, n=1, length=256, plant_frac=1.0)
+    for mb in (4, 64):
+        n_bytes = mb << 20
+        data = np.tile(piece, n_bytes // 256)
+        base_bit = int(rx.match_long(p, torch.from_numpy(data).to(dev), data.size).cpu().numpy()[0])
+        data[-256:] = member.data   # a member in the last 256 bytes: every chunk matters
+        d = torch.from_numpy(data).to(dev)
+        o = torch.tensor([0, data.size], dtype=torch.int64, device=dev)
+        entry = {"case": f"~200-node expression searched, one {mb} MiB string, one member in its last 256 bytes",
+                 "bit_without_member": base_bit}
+        if mb <= 4:
+            entry["serial_ms"], entry["serial_bit"] = timed(lambda: rx.match(p, d, o), reps=1)
+            entry["GBs_serial"] = round(data.size / (entry["serial_ms"] * 1e-3) / 1e9, 3)
+        entry["chunked_ms"], entry["chunked_bit"] = timed(lambda: rx.match_long(p, d, data.size))
+        entry["chunks"] = int(round((data.size / 20) ** 0.5)) if data.size / 20 < 4096 ** 2 else 4096
+        entry["GBs_chunked"] = round(data.size / (entry["chunked_ms"] * 1e-3) / 1e9, 2)
+        log(f"long: {entry}")
+        res["cases"].append(entry)
+    for family, k in (("nested", 819), ("altstar", 585)):
+        pk = W.pathological_program(family, k)
+        pp = rx.compile(pk.ast, pk.root).upload(dev)
+        n_len = 100_000
+        s = W.pathological_strings(family, n_len, count=2)
+        acc = torch.from_numpy(s.data[n_len:].copy()).to(dev)
+        entry = {"case": f"{family} 4,096 nodes, one string a^(n-1)t, n = 1e5"}
+        entry["serial_ms"], entry["serial_bit"] = timed(lambda: rx.match_fixed(pp, acc, n_len, 1), reps=1)
+        for ch in (16, 64):
+            entry[f"chunked_{ch}_ms"], entry[f"chunked_{ch}_bit"] = timed(lambda: rx.match_long(pp, acc, n_len, ch),
+                                                                       reps=1)
+        log(f"long: {entry}")
+        res["cases"].append(entry)
     return res
 
 
