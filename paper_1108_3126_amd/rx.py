@@ -182,6 +182,12 @@ def as_classes(classes) -> np.ndarray:
     return out
 
 
+def _keep_for_stream(t, stream):
+    """A temporary freed on return is reused by torch only after `stream` has passed this point."""
+    if stream is not None:
+        t.record_stream(stream)
+
+
 def _stream_handle(stream=None):
     import torch
 
@@ -365,6 +371,7 @@ def match_long(prog: Program, data, length: int = None, chunks: int = 0, out=Non
     need = _SZ()
     _check(lib().rx_match_long_workspace(prog.handle, int(length), int(chunks), ctypes.byref(need)))
     work = torch.empty(max(int(need.value), 4), dtype=torch.uint8, device=data.device)
+    _keep_for_stream(work, stream)
     if out is None:
         out = torch.empty(1, dtype=torch.uint8, device=data.device)
     dptr = ctypes.c_void_p(data.data_ptr() if data.numel() else work.data_ptr())
@@ -456,6 +463,7 @@ def match_multi(progs, data, offsets, out=None, config=None, work=None, stream=N
         _check(int(need))
     if work is None or work.numel() < need + 256:
         work = torch.empty(int(need) + 256, dtype=torch.uint8, device=offsets.device)
+        _keep_for_stream(work, stream)
     wptr = work.data_ptr() + ((-work.data_ptr()) % 256)
     if out is None:
         out = torch.empty((P, max(n, 0)), dtype=torch.uint8, device=offsets.device)
