@@ -255,8 +255,9 @@ int rx_match_first_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t
  * 16 words, one wavefront above; a second launch applies the relations in
  * order.  Work grows by the number of leaves, time falls by the number of
  * chunks: for strings far longer than the expression.
- * chunks: 0 = about sqrt(length / 20), else the count wanted (at most 4096
- * and at most length are used).  d_work: caller-owned device memory of at
+ * chunks: 0 = about sqrt(length / 2) for sets of at most 16 words and
+ * sqrt(length / 20) above, else the count wanted (at most 4096 and at most
+ * length are used).  d_work: caller-owned device memory of at
  * least rx_match_long_workspace bytes (the rows, u32 words).
  * Errors: RX_EINVAL (NULL buffers, negative sizes, short workspace),
  * RX_ENOTUPLOADED, RX_ETOOBIG (sets above 128 words), RX_EHIP. */

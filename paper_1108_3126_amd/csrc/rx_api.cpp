@@ -199,11 +199,14 @@ int rx_match(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_of
 }
 
 namespace {
-// Chunks of a chunk-parallel run: the requested count (0: about sqrt(length / 20),
-// which balances the rows' length against the composition's per-chunk cost),
-// at most 4096 and at most one per byte; every chunk holds at least one byte.
-void long_chunks(int64_t length, int32_t chunks, int64_t* C, int64_t* cl) {
-    int64_t c = chunks > 0 ? chunks : (int64_t)std::llround(std::sqrt((double)length / 20.0));
+// Chunks of a chunk-parallel run: the requested count, at most 4096 and at most
+// one per byte; every chunk holds at least one byte.  By default the count
+// balances the rows' time against the composition's (about 1 us per chunk):
+// lane rows all run at once, about 0.5 us per byte each, so C ~ sqrt(length / 2);
+// wavefront rows share the chip, so fewer chunks: C ~ sqrt(length / 20).
+void long_chunks(const Program* P, int64_t length, int32_t chunks, int64_t* C, int64_t* cl) {
+    const double per = P->W <= kLaneMaxWords ? 2.0 : 20.0;
+    int64_t c = chunks > 0 ? chunks : (int64_t)std::llround(std::sqrt((double)length / per));
     if (c > 4096) c = 4096;
     if (c > length) c = length;
     if (c < 1) c = 1;
@@ -222,7 +225,7 @@ int rx_match_long_workspace(const rx_program* prog, int64_t length, int32_t chun
     if (!P || !bytes) return fail(RX_EINVAL, "NULL argument");
     if (length < 0 || chunks < 0) return fail(RX_EINVAL, "negative length or chunk count");
     int64_t C, cl;
-    long_chunks(length, chunks, &C, &cl);
+    long_chunks(P, length, chunks, &C, &cl);
     *bytes = long_rows_bytes(P, C);
     return RX_OK;
     RX_GUARD_END
@@ -238,7 +241,7 @@ int rx_match_long(const rx_program* prog, const uint8_t* d_bytes, int64_t length
     if (!P->dev) return fail(RX_ENOTUPLOADED, "program has not been uploaded (rx_program_upload)");
     if (P->W > kWaveMaxWords) return fail(RX_ETOOBIG, "the wavefront kernel holds sets of at most 128 words");
     int64_t C, cl;
-    long_chunks(length, chunks, &C, &cl);
+    long_chunks(P, length, chunks, &C, &cl);
     const size_t need = long_rows_bytes(P, C);
     if (work_bytes < need)
         return fail(RX_EINVAL, "workspace holds " + std::to_string(work_bytes) + " bytes; this run needs " +

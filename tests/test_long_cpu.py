@@ -1,5 +1,6 @@
 """Host side of chunk-parallel matching: the workspace size follows the chunk rule (the requested count,
-at most 4096 and at most one chunk per byte, every chunk non-empty; by default about sqrt(length / 20))."""
+at most 4096 and at most one chunk per byte, every chunk non-empty; by default about sqrt(length / 2) for lane
+rows and sqrt(length / 20) for wavefront rows)."""
 import ctypes
 
 import pytest
@@ -28,7 +29,15 @@ def test_workspace_rule(search):
     assert ws(p, 10, 100) == (1 + 9 * (L + 1)) * row   # at most one chunk per byte
     assert ws(p, 1001, 10) == (1 + 9 * (L + 1)) * row  # chunks of 101 bytes: 10 non-empty
     assert ws(p, 1000, 7) == (1 + 6 * (L + 1)) * row   # chunks of 143 bytes: 7
-    assert ws(p, 200_000, 0) == (1 + 99 * (L + 1)) * row   # default: sqrt(200000 / 20) = 100
+    assert ws(p, 20_000, 0) == (1 + 99 * (L + 1)) * row   # default for lane rows: sqrt(20000 / 2) = 100
     assert ws(p, 1 << 40, 0) == (1 + 4095 * (L + 1)) * row  # capped at 4096
     with pytest.raises(rx.RxError):
         ws(p, -1, 0)
+
+
+def test_workspace_rule_wavefront_rows():
+    big = W.pathological_program("nested", 819)
+    p = rx.compile(big.ast, big.root)
+    L, Wd = p.info.n_leaves, p.info.words
+    assert Wd > 16
+    assert ws(p, 200_000, 0) == (1 + 99 * (L + 1)) * 4 * Wd   # sqrt(200000 / 20) = 100
