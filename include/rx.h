@@ -477,6 +477,14 @@ int rx_plain_match(const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx
 /* Thread-local message of the last failed call on this host thread. */
 const char* rx_last_error(void);
 
+/* 1 when entry points and server steps are wrapped in roctx ranges: the
+ * environment variable RX_ROCTX is set (not "0") when the library first
+ * looks, and a roctx library (librocprofiler-sdk-roctx or libroctx64) could
+ * be opened; then `rocprofv3 --marker-trace` shows each range ("rx_match",
+ * "rx_server.step", ...) around its kernels.  0 otherwise (ranges cost one
+ * branch).  Never fails. */
+int rx_trace_enabled(void);
+
 /* Measurement only: a plain coalesced device-to-device copy of `bytes`
  * (a multiple of 16; both buffers 16-byte aligned) on `stream`.  It gives the
  * practical streaming ceiling of the memory system and calibrates hardware

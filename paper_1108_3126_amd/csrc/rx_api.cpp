@@ -74,6 +74,7 @@ extern "C" {
 
 int rx_compile(const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx_class* classes,
                int32_t n_classes, uint32_t flags, rx_program** out) {
+    TraceRange trace_range_("rx_compile");
     RX_GUARD_BEGIN
     if (!out) return fail(RX_EINVAL, "out is NULL");
     *out = nullptr;
@@ -141,6 +142,7 @@ int rx_program_sets(const rx_program* prog, uint32_t* first, uint32_t* follow, u
 }
 
 int rx_program_upload(rx_program* prog, void* d_buf, size_t cap, void* stream) {
+    TraceRange trace_range_("rx_program_upload");
     RX_GUARD_BEGIN
     if (!prog || !d_buf) return fail(RX_EINVAL, "NULL argument");
     Program* P = reinterpret_cast<Program*>(prog);
@@ -160,6 +162,7 @@ int rx_program_upload(rx_program* prog, void* d_buf, size_t cap, void* stream) {
 
 int rx_match_ex(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t n,
                 uint8_t* d_out, const rx_launch* launch, void* stream) {
+    TraceRange trace_range_("rx_match_ex");
     RX_GUARD_BEGIN
     LaunchArgs a;
     if (int rc = make_launch_args(reinterpret_cast<const Program*>(prog), d_bytes, d_offsets, n, d_out, stream, &a)) return rc;
@@ -195,6 +198,7 @@ int rx_match_ex(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d
 
 int rx_match(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t n,
              uint8_t* d_out, void* stream) {
+    TraceRange trace_range_("rx_match");
     return rx_match_ex(prog, d_bytes, d_offsets, n, d_out, nullptr, stream);
 }
 
@@ -233,6 +237,7 @@ int rx_match_long_workspace(const rx_program* prog, int64_t length, int32_t chun
 
 int rx_match_long(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int32_t chunks, void* d_work,
                   size_t work_bytes, uint8_t* d_out, void* stream) {
+    TraceRange trace_range_("rx_match_long");
     RX_GUARD_BEGIN
     const Program* P = reinterpret_cast<const Program*>(prog);
     if (!P) return fail(RX_EINVAL, "program is NULL");
@@ -284,6 +289,7 @@ int rx_program_node_image(const rx_program* prog, void* buf, size_t cap, size_t*
 
 int rx_match_nodes(const rx_program* prog, const void* d_image, const uint8_t* d_bytes, const int64_t* d_offsets,
                    int64_t n, uint8_t* d_out, void* stream) {
+    TraceRange trace_range_("rx_match_nodes");
     RX_GUARD_BEGIN
     const Program* P = reinterpret_cast<const Program*>(prog);
     if (!P) return fail(RX_EINVAL, "program is NULL");
@@ -300,6 +306,7 @@ int rx_match_nodes(const rx_program* prog, const void* d_image, const uint8_t* d
 
 int rx_match_first_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int64_t n,
                          int64_t* d_first, void* stream) {
+    TraceRange trace_range_("rx_match_first_fixed");
     RX_GUARD_BEGIN
     const Program* P = reinterpret_cast<const Program*>(prog);
     if (!P) return fail(RX_EINVAL, "program is NULL");
@@ -338,6 +345,7 @@ int rx_match_first_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t
 
 int rx_match_first(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t n,
                    int64_t* d_first, void* stream) {
+    TraceRange trace_range_("rx_match_first");
     RX_GUARD_BEGIN
     LaunchArgs a;
     // the result bytes are not written: pass the position buffer through the checks
@@ -362,6 +370,7 @@ int rx_match_first(const rx_program* prog, const uint8_t* d_bytes, const int64_t
 
 int rx_match_fixed_ex(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int64_t n, uint8_t* d_out,
                       const rx_launch* launch, void* stream) {
+    TraceRange trace_range_("rx_match_fixed_ex");
     RX_GUARD_BEGIN
     const Program* P = reinterpret_cast<const Program*>(prog);
     if (length < 0) return fail(RX_EINVAL, "negative length");
@@ -419,6 +428,7 @@ int rx_match_fixed_ex(const rx_program* prog, const uint8_t* d_bytes, int64_t le
 
 int rx_match_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int64_t n, uint8_t* d_out,
                    void* stream) {
+    TraceRange trace_range_("rx_match_fixed");
     return rx_match_fixed_ex(prog, d_bytes, length, n, d_out, nullptr, stream);
 }
 
@@ -463,6 +473,7 @@ int64_t rx_match_multi_workspace(int64_t n, int32_t n_progs, const rx_multi_conf
 int rx_match_multi(const rx_program* const* progs, int32_t n_progs, const uint8_t* d_bytes,
                    const int64_t* d_offsets, int64_t n, uint8_t* d_out, void* d_work, size_t work_bytes,
                    const rx_multi_config* cfg, void* stream) {
+    TraceRange trace_range_("rx_match_multi");
     RX_GUARD_BEGIN
     if (n_progs <= 0 || !progs) return fail(RX_EINVAL, "no programs");
     if (n_progs > kMaxItemProgs) return fail(RX_ETOOBIG, "at most 64 programs per call");
@@ -536,6 +547,7 @@ int rx_autotune_multi(const rx_program* const* progs, int32_t n_progs, const uin
 }
 
 int rx_program_jit(rx_program* prog, const char* arch) {
+    TraceRange trace_range_("rx_program_jit");
     RX_GUARD_BEGIN
     if (!prog) return fail(RX_EINVAL, "program is NULL");
     int rc = jit_compile(reinterpret_cast<Program*>(prog), arch);
@@ -575,6 +587,8 @@ int rx_program_jit_staging(const rx_program* prog, int32_t staged[7]) {
 }
 
 const char* rx_last_error(void) { return last_error_cstr(); }
+
+int rx_trace_enabled(void) { return trace_enabled() ? 1 : 0; }
 
 int rx_stream_copy(void* d_dst, const void* d_src, int64_t bytes, void* stream) {
     if (bytes < 0 || (bytes % 16) != 0) return fail(RX_EINVAL, "bytes must be a non-negative multiple of 16");

@@ -122,6 +122,18 @@ int autotune_multi(const rx_program* const* progs, int32_t n_progs, const uint8_
                    int64_t n, uint8_t* d_out, void* d_work, size_t work_bytes, int budget_runs, rx_multi_config* best,
                    double* best_ms, int* n_cands, void* stream);
 
+// profiler ranges (rx_trace.cpp): a roctx range for the scope, when RX_ROCTX is set
+class TraceRange {
+public:
+    explicit TraceRange(const char* name);
+    ~TraceRange();
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+private:
+    bool on_;
+};
+bool trace_enabled();
+
 // error reporting (thread-local message)
 int fail(int code, const std::string& msg);
 void clear_error();

@@ -171,6 +171,7 @@ Server::~Server() {
 // Places the entry's tables in a device arena slot (evicting the least
 // recently used entry no running step reads); the copy is ordered on `s`.
 int Server::ensure_resident(CacheEntry* e, Slot& s) {
+    TraceRange trace_range_("rx_server.resident");
     if (e->arena_slot >= 0) {
         ++hits;
         return RX_OK;
@@ -197,6 +198,7 @@ int Server::ensure_resident(CacheEntry* e, Slot& s) {
 }
 
 bool Server::launch_step(Slot& s, std::vector<Request*>& take) {
+    TraceRange trace_range_("rx_server.step");
     const Clock::time_point t0 = Clock::now();
     ++step_seq;
     hipEventRecord(s.start_ev, s.stream);
@@ -294,6 +296,7 @@ bool Server::launch_step(Slot& s, std::vector<Request*>& take) {
 }
 
 void Server::complete(Slot& s) {
+    TraceRange trace_range_("rx_server.complete");
     const Clock::time_point now = Clock::now();
     float dev_ms = 0;
     hipEventElapsedTime(&dev_ms, s.start_ev, s.done_ev);

@@ -102,6 +102,7 @@ SIGNATURES = {
     "rx_match_first_fixed": (ctypes.c_int, [_VP, _VP, _I64, _I64, _VP, _VP]),
     "rx_program_node_image": (ctypes.c_int, [_VP, _VP, _SZ, ctypes.POINTER(_SZ)]),
     "rx_match_long_workspace": (ctypes.c_int, [_VP, _I64, _I32, ctypes.POINTER(_SZ)]),
+    "rx_trace_enabled": (ctypes.c_int, []),
     "rx_match_long": (ctypes.c_int, [_VP, _VP, _I64, _I32, _VP, _SZ, _VP, _VP]),
     "rx_match_nodes": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I64, _VP, _VP]),
     "rx_parse": (ctypes.c_int, [ctypes.c_char_p, _SZ, _VP, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _VP, _I32,
