@@ -401,6 +401,49 @@ __global__ __launch_bounds__(1024) void k_compose(const uint32_t* __restrict__ T
     if (tid == 0) out[0] = (S[aw] & abit) ? 1 : 0;
 }
 
+// The same for sets of at most 16 words (at most 512 rows per chunk): one row
+// per thread, and each thread loads its row of the next chunk while the
+// current chunk is applied, so the loads' latency is off the chain.
+template <int W>
+__global__ __launch_bounds__(512) void k_compose_lane(const uint32_t* __restrict__ T, int64_t chunks, int32_t rpc,
+                                                      int32_t L, int32_t suffix_any, uint8_t* __restrict__ out) {
+    __shared__ uint32_t S[W], N[W];
+    const int tid = threadIdx.x;
+    const bool own = tid < rpc;
+    const int aw = L >> 5;
+    const uint32_t abit = 1u << (L & 31);
+    if (tid < W) S[tid] = T[tid];
+    uint32_t cur[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) cur[w] = (own && chunks > 1) ? T[(1 + (int64_t)tid) * W + w] : 0u;
+    __syncthreads();
+    for (int64_t c = 1; c < chunks; ++c) {
+        uint32_t nxt[W];
+        const bool more = own && c + 1 < chunks;
+        const uint32_t* nrow = T + (1 + c * (int64_t)rpc + tid) * W;
+#pragma unroll
+        for (int w = 0; w < W; ++w) nxt[w] = more ? nrow[w] : 0u;
+        uint32_t any = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) any |= S[w];
+        if (any == 0) break;                          // no live thread: reject
+        if (suffix_any && (S[aw] & abit)) break;      // accept is absorbing
+        if (tid < W) N[tid] = 0;
+        __syncthreads();
+        if (own && ((S[tid >> 5] >> (tid & 31)) & 1u)) {
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                if (cur[w]) atomicOr(&N[w], cur[w]);
+        }
+        __syncthreads();
+        if (tid < W) S[tid] = N[tid];
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < W; ++w) cur[w] = nxt[w];
+    }
+    if (tid == 0) out[0] = (S[aw] & abit) ? 1 : 0;
+}
+
 // Streaming copy (measurement only): the practical HBM ceiling and the
 // calibration of byte counters against a kernel of known traffic.
 __global__ __launch_bounds__(256) void k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16) {
@@ -412,6 +455,21 @@ int launch_compose(const uint32_t* rows, int64_t chunks, int32_t rpc, int32_t W,
                    uint8_t* out, void* stream) {
     int threads = ((rpc + 63) / 64) * 64;
     if (threads > 1024) threads = 1024;
+    if (W <= kLaneMaxWords && rpc <= 512) {
+        switch (W) {
+#define RX_COMPOSE_CASE(w)                                                                                        \
+    case w:                                                                                                       \
+        hipLaunchKernelGGL((k_compose_lane<w>), dim3(1), dim3(threads), 0, (hipStream_t)stream, rows, chunks, rpc, L, \
+                           suffix_any, out);                                                                      \
+        return (int)hipGetLastError();
+            RX_COMPOSE_CASE(1) RX_COMPOSE_CASE(2) RX_COMPOSE_CASE(3) RX_COMPOSE_CASE(4) RX_COMPOSE_CASE(5)
+            RX_COMPOSE_CASE(6) RX_COMPOSE_CASE(7) RX_COMPOSE_CASE(8) RX_COMPOSE_CASE(9) RX_COMPOSE_CASE(10)
+            RX_COMPOSE_CASE(11) RX_COMPOSE_CASE(12) RX_COMPOSE_CASE(13) RX_COMPOSE_CASE(14) RX_COMPOSE_CASE(15)
+            RX_COMPOSE_CASE(16)
+#undef RX_COMPOSE_CASE
+        default: break;
+        }
+    }
     hipLaunchKernelGGL(k_compose, dim3(1), dim3(threads), 0, (hipStream_t)stream, rows, chunks, rpc, W, L, suffix_any,
                        out);
     return (int)hipGetLastError();
