@@ -240,8 +240,11 @@ int rx_match_first(const rx_program* prog, const uint8_t* d_bytes, const int64_t
  * (i+1)*length)).  With a compiled circuit (rx_program_jit), 16-byte aligned
  * bytes and length % 16 == 0 (length <= 2^26), the skewed bit-sliced kernel
  * runs, recording each string's first accept as it appears; otherwise the
- * table-form kernels.  A program whose root is nullable answers 0 for every
- * string without matching.  Errors as rx_match_fixed. */
+ * table-form kernels.  d_first: caller-owned device int64[n]; entry i = the
+ * length of the shortest prefix of string i that the program accepts (with
+ * RX_SEARCH: where the earliest-ending match ends), -1 if none.  A program
+ * whose root is nullable answers 0 for every string without matching.
+ * Asynchronous on stream; allocates nothing.  Errors as rx_match_fixed. */
 int rx_match_first_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int64_t n,
                          int64_t* d_first, void* stream);
 
@@ -258,7 +261,10 @@ int rx_match_first_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t
  * chunks: 0 = about sqrt(length / 2) for sets of at most 16 words and
  * sqrt(length / 20) above, else the count wanted (at most 4096 and at most
  * length are used).  d_work: caller-owned device memory of at
- * least rx_match_long_workspace bytes (the rows, u32 words).
+ * least rx_match_long_workspace bytes (the rows, u32 words), overwritten;
+ * d_out: caller-owned device byte, 0 or 1.  Asynchronous on stream: d_bytes
+ * and d_work stay in use until the stream passes the call; allocates
+ * nothing.  Length 0 gives the nullable bit.
  * Errors: RX_EINVAL (NULL buffers, negative sizes, short workspace),
  * RX_ENOTUPLOADED, RX_ETOOBIG (sets above 128 words), RX_EHIP. */
 int rx_match_long_workspace(const rx_program* prog, int64_t length, int32_t chunks, size_t* bytes);
@@ -284,7 +290,10 @@ int rx_match_long(const rx_program* prog, const uint8_t* d_bytes, int64_t length
  * Errors: RX_EINVAL (NULL arguments, short buffer). */
 int rx_program_node_image(const rx_program* prog, void* buf, size_t cap, size_t* len);
 
-/* Strings as in rx_match; asynchronous on stream.
+/* Strings as in rx_match (d_bytes, d_offsets[n + 1]); d_out: caller-owned
+ * device uint8[n], 0 or 1 per string.  Reads only d_image, not the uploaded
+ * tables, so rx_program_upload is not needed.  Asynchronous on stream;
+ * allocates nothing.
  * Errors: RX_EINVAL (NULL buffers, n < 0), RX_ETOOBIG (more than 8191 nodes:
  * two 8-byte stamps per node in LDS), RX_EHIP. */
 int rx_match_nodes(const rx_program* prog, const void* d_image, const uint8_t* d_bytes, const int64_t* d_offsets,
