@@ -52,10 +52,10 @@ struct NodeRec {
 
 typedef unsigned long long u64;
 
-__device__ __forceinline__ void send(u64* c, int q, int m, u64 S, u64 g, u64* act) {   // act: this round's slot
+__device__ __forceinline__ void send(u64* c, int q, int m, u64 S, u64 g, u64* act) {   // act: the activity slot of this pass
     if (q == -2) return;                               // no message
     const int idx = q < 0 ? m : q;                     // -1: null
-    if (atomicMax(&c[idx], S) < S) *act = g;           // a fresh receiver: more work this round
+    if (atomicMax(&c[idx], S) < S) *act = g;           // a fresh receiver: another pass is needed
 }
 
 __global__ __launch_bounds__(1024) void k_nodes(const int32_t* __restrict__ image, const uint8_t* __restrict__ bytes,
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(1024) void k_nodes(const int32_t* __restrict__ imag
                     }
                 }
                 __syncthreads();
-                if (*a != g) break;   // no node was scheduled this round: the step is quiescent
+                if (*a != g) break;   // no node was scheduled in this pass: the step is quiescent
             }
             if (t == len) {   // input spent: accept iff null has received a message
                 accept = c[m] >= S;
