@@ -18,7 +18,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     f"--offload-arch={ARCH}",
     # no packed-FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -37,17 +36,35 @@ def sources():
     return [os.path.join(CSRC, s) for s in srcs]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source into paper_1108_3126_amd/librx.so (always rebuilds)."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}", *sources(),
-           "-o", tmp, "-lhiprtc", "-lpthread"]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
+    return subprocess.run(cmd, capture_output=True, text=True)
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source into paper_1108_3126_amd/librx.so (always rebuilds): one object per source,
+    compiled in parallel, then one link."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    srcs = sources()
+    objs = [os.path.join(objdir, os.path.basename(s) + ".o") for s in srcs]
+    inc = [f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
+    jobs = jobs or max(1, min(len(srcs), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(lambda so: _run([HIPCC, *FLAGS, *inc, "-c", so[0], "-o", so[1]], verbose),
+                              zip(srcs, objs)))
+    for src, res in zip(srcs, results):
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError(f"hipcc failed on {os.path.basename(src)}")
+    tmp = LIB + ".tmp"
+    res = _run([HIPCC, *FLAGS, "-shared", *objs, "-o", tmp, "-lhiprtc", "-lpthread"], verbose)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed to build librx.so")
+        raise RuntimeError("hipcc failed to link librx.so")
     os.replace(tmp, LIB)
     return LIB
 
