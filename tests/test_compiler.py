@@ -205,3 +205,13 @@ def test_match_without_upload_is_an_error():
     assert rc == rx.RX_ENOTUPLOADED
     assert L.rx_match(p.handle, None, None, 0, None, None) == rx.RX_ENOTUPLOADED
     assert L.rx_match(None, None, None, 0, None, None) == rx.RX_EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """No fallback: without the built library every entry point raises instead of computing elsewhere."""
+    monkeypatch.setattr(rx, "_lib", None)
+    monkeypatch.setattr(rx, "LIB_PATH", os.path.join(ROOT, "no-such-dir", "librx.so"))
+    with pytest.raises(ImportError):
+        rx.compile_regex(b"ab")
+    with pytest.raises(ImportError):
+        rx.parse(b"a*b")
