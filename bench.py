@@ -382,7 +382,7 @@ def run_pathological(args, torch, dev):
         log(f"pathological {family} k scaling at n=1e4: {scale}")
         # the paper's node-per-thread machine (one workgroup per string, one thread per node)
         nm = {}
-        for n_len in (1000, 10000):
+        for n_len in (1000, 10000, 100000):
             s = W.pathological_strings(family, n_len, count=256)
             d, o = torch.from_numpy(s.data).to(dev), torch.from_numpy(s.offsets).to(dev)
             out = rx.match_nodes(p, d, o)
@@ -398,6 +398,9 @@ def run_pathological(args, torch, dev):
             log(f"pathological {family} node machine n={n_len}: {nm[str(n_len)]}")
             if nm[str(n_len)]["ms"] > 2000:
                 break
+        if "100000" in nm:
+            nm["ratio_1e5_1e4"] = round(nm["100000"]["ms"] / nm["10000"]["ms"], 2)
+        nm["ratio_1e4_1e3"] = round(nm["10000"]["ms"] / nm["1000"]["ms"], 2)
         fam["node_machine"] = nm
         res["families"][family] = fam
     return res
