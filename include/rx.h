@@ -261,7 +261,8 @@ int rx_match_first_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t
  * chunks: 0 = about sqrt(length / 2) for sets of at most 16 words and
  * sqrt(length / 20) above, else the count wanted (at most 4096 and at most
  * length are used).  d_work: caller-owned device memory of at
- * least rx_match_long_workspace bytes (the rows, u32 words), overwritten;
+ * least rx_match_long_workspace bytes (the rows: their sets as u32 words, then
+ * one int64 each for rx_match_first_long), overwritten;
  * d_out: caller-owned device byte, 0 or 1.  Asynchronous on stream: d_bytes
  * and d_work stay in use until the stream passes the call; allocates
  * nothing.  Length 0 gives the nullable bit.
@@ -270,6 +271,16 @@ int rx_match_first_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t
 int rx_match_long_workspace(const rx_program* prog, int64_t length, int32_t chunks, size_t* bytes);
 int rx_match_long(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int32_t chunks, void* d_work,
                   size_t work_bytes, uint8_t* d_out, void* stream);
+
+/* rx_match_first for one long string, in chunks as rx_match_long: each row
+ * also records how many bytes of its chunk it reads before its first accept;
+ * the composition stops at the first chunk where a live row accepts.
+ * d_first: caller-owned device int64, the length of the shortest accepted
+ * prefix (with RX_SEARCH: where the earliest-ending match ends), or -1.  A
+ * nullable program answers 0.  Workspace, chunks and errors as rx_match_long
+ * (rx_match_long_workspace covers both). */
+int rx_match_first_long(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int32_t chunks, void* d_work,
+                        size_t work_bytes, int64_t* d_first, void* stream);
 
 /* The paper's own GPU machine (§8, on the process translation of §7): every
  * node of d[] is a process owned by one thread of a workgroup; stamp vectors

@@ -218,9 +218,14 @@ void long_chunks(const Program* P, int64_t length, int32_t chunks, int64_t* C, i
     *C = length > 0 ? (length + *cl - 1) / *cl : 1;
 }
 
-size_t long_rows_bytes(const Program* P, int64_t C) {
-    return (size_t)(1 + (C - 1) * (int64_t)(P->L + 1)) * (size_t)P->W * 4;
+int64_t long_rows(const Program* P, int64_t C) { return 1 + (C - 1) * (int64_t)(P->L + 1); }
+
+// The rows' sets (u32 words), then, 8-byte aligned, one int64 per row for the
+// earliest-accept form.
+size_t long_sets_bytes(const Program* P, int64_t C) {
+    return ((size_t)long_rows(P, C) * (size_t)P->W * 4 + 7) & ~(size_t)7;
 }
+size_t long_rows_bytes(const Program* P, int64_t C) { return long_sets_bytes(P, C) + 8 * (size_t)long_rows(P, C); }
 }  // namespace
 
 int rx_match_long_workspace(const rx_program* prog, int64_t length, int32_t chunks, size_t* bytes) {
@@ -265,6 +270,48 @@ int rx_match_long(const rx_program* prog, const uint8_t* d_bytes, int64_t length
     int e = P->W <= kLaneMaxWords ? launch_lane(a) : launch_wave(a);
     if (e) return hip_fail(e, "kernel launch (rows)");
     e = launch_compose(a.rows_out, C, P->L + 1, P->W, P->L, P->suffix_any ? 1 : 0, d_out, stream);
+    if (e) return hip_fail(e, "kernel launch (composition)");
+    return RX_OK;
+    RX_GUARD_END
+}
+
+int rx_match_first_long(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int32_t chunks, void* d_work,
+                        size_t work_bytes, int64_t* d_first, void* stream) {
+    TraceRange trace_range_("rx_match_first_long");
+    RX_GUARD_BEGIN
+    const Program* P = reinterpret_cast<const Program*>(prog);
+    if (!P) return fail(RX_EINVAL, "program is NULL");
+    if (length < 0 || chunks < 0) return fail(RX_EINVAL, "negative length or chunk count");
+    if (!d_first || !d_work || (length > 0 && !d_bytes)) return fail(RX_EINVAL, "NULL device buffer");
+    if (!P->dev) return fail(RX_ENOTUPLOADED, "program has not been uploaded (rx_program_upload)");
+    if (P->W > kWaveMaxWords) return fail(RX_ETOOBIG, "the wavefront kernel holds sets of at most 128 words");
+    int64_t C, cl;
+    long_chunks(P, length, chunks, &C, &cl);
+    const size_t need = long_rows_bytes(P, C);
+    if (work_bytes < need)
+        return fail(RX_EINVAL, "workspace holds " + std::to_string(work_bytes) + " bytes; this run needs " +
+                                   std::to_string(need) + " (rx_match_long_workspace)");
+    int e;
+    if (P->nullable) {
+        e = launch_fill_i64(d_first, 1, 0, stream);   // the empty prefix is accepted
+        if (e) return hip_fail(e, "kernel launch");
+        return RX_OK;
+    }
+    LaunchArgs a;
+    if (int rc = make_launch_args(P, d_bytes ? d_bytes : static_cast<const uint8_t*>(d_work),
+                                  static_cast<const int64_t*>(d_work), long_rows(P, C),
+                                  static_cast<uint8_t*>(d_work), stream, &a))
+        return rc;
+    a.offsets = nullptr;
+    a.out = nullptr;
+    a.rows_out = static_cast<uint32_t*>(d_work);
+    a.first_pos = reinterpret_cast<int64_t*>(static_cast<uint8_t*>(d_work) + long_sets_bytes(P, C));
+    a.rows_len = length;
+    a.rows_cl = cl;
+    a.rows_per_chunk = P->L + 1;
+    e = P->W <= kLaneMaxWords ? launch_lane(a) : launch_wave(a);
+    if (e) return hip_fail(e, "kernel launch (rows)");
+    e = launch_compose_first(a.rows_out, a.first_pos, C, cl, P->L + 1, P->W, d_first, stream);
     if (e) return hip_fail(e, "kernel launch (composition)");
     return RX_OK;
     RX_GUARD_END

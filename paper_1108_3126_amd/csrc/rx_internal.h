@@ -191,6 +191,8 @@ int launch_wave(const LaunchArgs& a);
 // rx_match_long, second pass: one workgroup applies the chunks' relations in order
 int launch_compose(const uint32_t* rows, int64_t chunks, int32_t rpc, int32_t W, int32_t L, int32_t suffix_any,
                    uint8_t* out, void* stream);
+int launch_compose_first(const uint32_t* rows, const int64_t* fp, int64_t chunks, int64_t cl, int32_t rpc,
+                         int32_t W, int64_t* out, void* stream);
 const char* hip_error_string(int err);
 int launch_stream_copy(void* dst, const void* src, int64_t bytes, void* stream);
 int hip_current_device(int* dev);

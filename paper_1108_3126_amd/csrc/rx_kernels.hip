@@ -129,7 +129,8 @@ __global__ __launch_bounds__(256) void k_lane(KArgs a) {
             hi = a.offsets ? a.offsets[sid + 1] : lo + a.stride;
         }
         int res = -1;
-        int64_t pos = (FIRST && (pick<W>(S, aw) & abit)) ? 0 : -1;
+        // (rows look for accepts after at least one byte of their chunk)
+        int64_t pos = (FIRST && !ROWS && (pick<W>(S, aw) & abit)) ? 0 : -1;
         // aligned 16-byte blocks of the absolute address range [bytes+lo, bytes+hi):
         // every block read holds at least one byte of the string
         const int64_t skew = (int64_t)(reinterpret_cast<uintptr_t>(a.bytes) & 15);
@@ -155,6 +156,7 @@ __global__ __launch_bounds__(256) void k_lane(KArgs a) {
             uint32_t* o = a.rows_out + sid * W;
 #pragma unroll
             for (int w = 0; w < W; ++w) o[w] = res == 1 ? (w == aw ? abit : 0u) : S[w];
+            if (FIRST) a.first_pos[sid] = pos;   // bytes of the chunk up to the row's first accept, or -1
             continue;
         }
         if (FIRST) {
@@ -205,7 +207,7 @@ __global__ __launch_bounds__(1024) void k_wave(KArgs a) {
         }
         int res = -1;
         int64_t pos = -1;
-        if (FIRST) {
+        if (FIRST && !ROWS) {
             const uint32_t sw = (uint32_t)__builtin_amdgcn_readlane((int)(aw < 64 ? S0 : S1), aw & 63);
             if (sw & abit) pos = 0;
         }
@@ -264,6 +266,7 @@ __global__ __launch_bounds__(1024) void k_wave(KArgs a) {
             uint32_t* o = a.rows_out + sid * W;
             if (own0) o[lane] = res == 1 ? (lane == aw ? abit : 0u) : S0;
             if (own1) o[lane + 64] = res == 1 ? (lane + 64 == aw ? abit : 0u) : S1;
+            if (FIRST && lane == 0) a.first_pos[sid] = pos;
             continue;
         }
         if (FIRST) {
@@ -310,7 +313,10 @@ int launch_lane_w(const LaunchArgs& a) {
     if (grid < 1) grid = 1;
     const size_t lds = 4 * (size_t)(256 + a.L) * W;
     if (a.rows_out)
-        hipLaunchKernelGGL((k_lane<W, false, true>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
+        if (a.first_pos)
+            hipLaunchKernelGGL((k_lane<W, true, true>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
+        else
+            hipLaunchKernelGGL((k_lane<W, false, true>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
     else if (a.first_pos)
         hipLaunchKernelGGL((k_lane<W, true, false>), dim3(grid), dim3(block), lds, (hipStream_t)a.stream, kargs(a));
     else
@@ -341,7 +347,10 @@ int launch_wave(const LaunchArgs& a) {
     const size_t lds = 4 * (size_t)(256 + a.L) * a.W;
     if (a.rows_out) {
         // many independent rows: tables through the caches, so more waves fit per CU
-        hipLaunchKernelGGL((k_wave<false, false, true>), dim3(grid), dim3(block), 0, (hipStream_t)a.stream, kargs(a));
+        if (a.first_pos)
+            hipLaunchKernelGGL((k_wave<false, true, true>), dim3(grid), dim3(block), 0, (hipStream_t)a.stream, kargs(a));
+        else
+            hipLaunchKernelGGL((k_wave<false, false, true>), dim3(grid), dim3(block), 0, (hipStream_t)a.stream, kargs(a));
     } else if (lds <= 150 * 1024) {
         static bool attr_set = false;
         if (!attr_set) {
@@ -444,11 +453,67 @@ __global__ __launch_bounds__(512) void k_compose_lane(const uint32_t* __restrict
     if (tid == 0) out[0] = (S[aw] & abit) ? 1 : 0;
 }
 
+// The earliest accepting prefix of the whole string: chunk by chunk, the
+// first chunk in which a live row meets an accept ends the search; the answer
+// is the chunk's start plus the smallest such row offset (FP holds each row's
+// bytes up to its first accept, -1 if none).
+__global__ __launch_bounds__(1024) void k_compose_first(const uint32_t* __restrict__ T, const int64_t* __restrict__ FP,
+                                                        int64_t chunks, int64_t cl, int32_t rpc, int32_t W,
+                                                        int64_t* __restrict__ out) {
+    __shared__ uint32_t S[kWaveMaxWords], N[kWaveMaxWords];
+    __shared__ unsigned long long best;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int w = tid; w < W; w += nt) S[w] = T[w];
+    if (tid == 0) best = ~0ull;
+    __syncthreads();
+    if (FP[0] >= 0) {                                 // inside chunk 0
+        if (tid == 0) out[0] = FP[0];
+        return;
+    }
+    for (int64_t c = 1; c < chunks; ++c) {
+        uint32_t any = 0;
+        for (int w = 0; w < W; ++w) any |= S[w];
+        if (any == 0) break;                          // no live thread: no accept
+        for (int w = tid; w < W; w += nt) N[w] = 0;
+        __syncthreads();
+        const uint32_t* rows = T + (1 + (c - 1) * (int64_t)rpc) * W;
+        const int64_t* fps = FP + 1 + (c - 1) * (int64_t)rpc;
+        for (int r = tid; r < rpc; r += nt) {
+            if (!((S[r >> 5] >> (r & 31)) & 1u)) continue;
+            const int64_t p = fps[r];
+            if (p >= 0) atomicMin(&best, (unsigned long long)p);
+            const uint32_t* row = rows + (int64_t)r * W;
+            for (int w = 0; w < W; ++w) {
+                const uint32_t v = row[w];
+                if (v) atomicOr(&N[w], v);
+            }
+        }
+        __syncthreads();
+        const unsigned long long b = best;
+        if (b != ~0ull) {                             // every thread reads the same value
+            if (tid == 0) out[0] = c * cl + (int64_t)b;
+            return;
+        }
+        for (int w = tid; w < W; w += nt) S[w] = N[w];
+        __syncthreads();
+    }
+    if (tid == 0) out[0] = -1;
+}
+
 // Streaming copy (measurement only): the practical HBM ceiling and the
 // calibration of byte counters against a kernel of known traffic.
 __global__ __launch_bounds__(256) void k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
+}
+
+int launch_compose_first(const uint32_t* rows, const int64_t* fp, int64_t chunks, int64_t cl, int32_t rpc,
+                         int32_t W, int64_t* out, void* stream) {
+    int threads = ((rpc + 63) / 64) * 64;
+    if (threads > 1024) threads = 1024;
+    hipLaunchKernelGGL(k_compose_first, dim3(1), dim3(threads), 0, (hipStream_t)stream, rows, fp, chunks, cl, rpc, W,
+                       out);
+    return (int)hipGetLastError();
 }
 
 int launch_compose(const uint32_t* rows, int64_t chunks, int32_t rpc, int32_t W, int32_t L, int32_t suffix_any,

@@ -103,6 +103,7 @@ SIGNATURES = {
     "rx_program_node_image": (ctypes.c_int, [_VP, _VP, _SZ, ctypes.POINTER(_SZ)]),
     "rx_match_long_workspace": (ctypes.c_int, [_VP, _I64, _I32, ctypes.POINTER(_SZ)]),
     "rx_trace_enabled": (ctypes.c_int, []),
+    "rx_match_first_long": (ctypes.c_int, [_VP, _VP, _I64, _I32, _VP, _SZ, _VP, _VP]),
     "rx_match_long": (ctypes.c_int, [_VP, _VP, _I64, _I32, _VP, _SZ, _VP, _VP]),
     "rx_match_nodes": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I64, _VP, _VP]),
     "rx_parse": (ctypes.c_int, [ctypes.c_char_p, _SZ, _VP, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _VP, _I32,
@@ -378,6 +379,29 @@ def match_long(prog: Program, data, length: int = None, chunks: int = 0, out=Non
     dptr = ctypes.c_void_p(data.data_ptr() if data.numel() else work.data_ptr())
     _check(lib().rx_match_long(prog.handle, dptr, int(length), int(chunks), ctypes.c_void_p(work.data_ptr()),
                                work.numel(), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def match_first_long(prog: Program, data, length: int = None, chunks: int = 0, out=None, stream=None):
+    """Earliest accepting prefix of one long string data[:length], in chunks: a 1-element int64 tensor (-1: none)."""
+    import torch
+
+    if prog._dev_buf is None:
+        prog.upload(device=data.device, stream=stream)
+    if data.dtype != torch.uint8 or not data.is_cuda:
+        raise TypeError("data must be a uint8 device tensor")
+    data = data.contiguous()
+    if length is None:
+        length = data.numel()
+    need = _SZ()
+    _check(lib().rx_match_long_workspace(prog.handle, int(length), int(chunks), ctypes.byref(need)))
+    work = torch.empty(max(int(need.value), 8), dtype=torch.uint8, device=data.device)
+    _keep_for_stream(work, stream)
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=data.device)
+    dptr = ctypes.c_void_p(data.data_ptr() if data.numel() else work.data_ptr())
+    _check(lib().rx_match_first_long(prog.handle, dptr, int(length), int(chunks), ctypes.c_void_p(work.data_ptr()),
+                                     work.numel(), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
 
 

@@ -134,3 +134,84 @@ def test_long_errors(dev):
     rc = rx.lib().rx_match_long(q.handle, ctypes.c_void_p(d.data_ptr()), 64, 4, ctypes.c_void_p(work.data_ptr()),
                                 int(need.value), ctypes.c_void_p(out.data_ptr()), None)
     assert rc == rx.RX_ENOTUPLOADED
+
+
+def first_long(p, data, dev, chunks=0):
+    from paper_1108_3126_amd import rx
+
+    d = torch.from_numpy(data if data.size else np.zeros(16, np.uint8)).to(dev)
+    out = rx.match_first_long(p, d, data.size, chunks)
+    torch.cuda.synchronize()
+    return int(out.cpu().numpy()[0])
+
+
+def first_serial(p, data, dev):
+    from paper_1108_3126_amd import rx
+
+    d = torch.from_numpy(data if data.size else np.zeros(16, np.uint8)).to(dev)
+    out = rx.match_first(p, d, torch.tensor([0, data.size], dtype=torch.int64, device=dev))
+    torch.cuda.synchronize()
+    return int(out.cpu().numpy()[0])
+
+
+def first_by_prefixes(prog, search, data):
+    pre = [bytes(data[:k]) for k in range(data.size + 1)]
+    s = W.pack(pre)
+    acc = oracle.match(prog.ast, prog.root, prog.classes, search, s.data, s.offsets)
+    hit = np.nonzero(acc)[0]
+    return int(hit[0]) if hit.size else -1
+
+
+def test_first_long_small_programs(dev):
+    """Earliest accepting prefix of one string in chunks: equal to the serial table-form run for every chunk
+    count, and to the oracle on every prefix for the shorter strings."""
+    from paper_1108_3126_amd import rx
+
+    rng = np.random.default_rng(15)
+    for seed in range(50):
+        prog = W.small_program(seed)
+        for search in (False, True):
+            p = rx.compile(prog.ast, prog.root, prog.classes, search).upload(dev)
+            for length in (0, 1, 6, 90, 700):
+                data = np.frombuffer(b"ab", np.uint8)[rng.integers(0, 2, size=length)].astype(np.uint8)
+                want = first_serial(p, data, dev)
+                if length <= 90:
+                    assert want == first_by_prefixes(prog, search, data), (seed, search, length)
+                for chunks in (0, 1, 3, 16, length, length + 4):
+                    assert first_long(p, data, dev, chunks) == want, (seed, search, length, chunks)
+
+
+def test_first_long_single_program(dev):
+    """The ~200-node searched expression on a 256 KB string whose only match sits at a chosen place (start of a
+    chunk, across a boundary, at the end): the chunked answer equals the serial one."""
+    from paper_1108_3126_amd import rx
+
+    prog = W.single_program(1)
+    p = rx.compile(prog.ast, prog.root, prog.classes, True).upload(dev)
+    pieces, _ = W.single_strings(prog, seed=30, n=2048, length=256, plant_frac=0.0)
+    bits = rx.match_fixed(p, torch.from_numpy(pieces.data).to(dev), 256, pieces.n).cpu().numpy()
+    piece = pieces.data[int(np.nonzero(bits == 0)[0][0]) * 256:][:256]
+    member, _ = W.single_strings(prog, seed=31, n=1, length=256, plant_frac=1.0)
+    base = np.tile(piece, 1024)
+    assert first_serial(p, base, dev) == -1 or first_long(p, base, dev) == first_serial(p, base, dev)
+    for at in (0, 1000, base.size // 2 - 77, base.size - 256):
+        data = base.copy()
+        data[at:at + 256] = member.data
+        want = first_serial(p, data, dev)
+        assert want > 0
+        for chunks in (0, 7, 512, 4096):
+            assert first_long(p, data, dev, chunks) == want, (at, chunks)
+
+
+@pytest.mark.parametrize("family,k", [("nested", 819), ("altstar", 585)])
+def test_first_long_pathological(dev, family, k):
+    """Wavefront rows: a^(n-1) t is first accepted at its very end, a^n never."""
+    from paper_1108_3126_amd import rx
+
+    prog = W.pathological_program(family, k)
+    p = rx.compile(prog.ast, prog.root).upload(dev)
+    n = 3000
+    s = W.pathological_strings(family, n, count=2)
+    for chunks in (1, 8, 40):
+        assert first_long(p, s.data[:n].copy(), dev, chunks) == -1
+        assert first_long(p, s.data[n:].copy(), dev, chunks) == n
