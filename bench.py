@@ -451,6 +451,7 @@ def run_long(args, torch, dev):
             entry["serial_ms"], entry["serial_bit"] = timed(lambda: rx.match(p, d, o), reps=1)
             entry["GBs_serial"] = round(data.size / (entry["serial_ms"] * 1e-3) / 1e9, 3)
         entry["chunked_ms"], entry["chunked_bit"] = timed(lambda: rx.match_long(p, d, data.size))
+        entry["first_chunked_ms"], entry["first_chunked"] = timed(lambda: rx.match_first_long(p, d, data.size))
         entry["chunks"] = min(int(round((data.size / 2) ** 0.5)), 4096)
         entry["GBs_chunked"] = round(data.size / (entry["chunked_ms"] * 1e-3) / 1e9, 2)
         log(f"long: {entry}")
