@@ -367,6 +367,32 @@ int rx_program_jit_stats(const rx_program* prog, int32_t* ready, int32_t* state_
  * Errors: RX_EINVAL (NULL arguments). */
 int rx_program_jit_staging(const rx_program* prog, int32_t staged[7]);
 
+/* The static check behind the register-staged sliced kernels (staging modes
+ * 1, 3, 4, 5 and the earliest-accept form).  Those kernels keep loads in
+ * flight in accumulation registers written by inline assembly, which the
+ * device compiler takes as present at once; rx_program_jit disassembles the
+ * generated code object and keeps such a kernel only if no instruction other
+ * than its own 16-byte global loads and 16-byte LDS writes names an
+ * accumulation register (so nothing copies, spills or moves one before its
+ * load lands).  *ran = 1 when the check ran (0: the disassembler was not
+ * available, and every staged kernel is dropped); violations[k] = the number
+ * of offending instructions in staged kernel k (-1: not checked) for k = 0..6
+ * in the order mode 1, mode 3, mode 4, mode 5 (pair reads), mode 5
+ * (single-dword reads), earliest accept (pair reads), earliest accept
+ * (single-dword reads); violations[7] is unused; *dropped has bit k set when
+ * kernel k was dropped by the check (it never runs; the staging report above
+ * shows what runs instead).  Errors: RX_EINVAL (NULL arguments). */
+int rx_program_jit_guard(const rx_program* prog, int32_t* ran, int32_t violations[8], int32_t* dropped);
+
+/* The same check on any code object (an AMDGPU ELF of len bytes, owned by the
+ * caller) for the function `kernel` compiled for `arch` (e.g. "gfx950"):
+ * *violations = instructions that name an accumulation register other than
+ * 16-byte global loads and 16-byte LDS writes.  Returns RX_OK when the check
+ * ran (the message of rx_last_error then names the first offending
+ * instruction, if any); RX_EINVAL when it could not (no disassembler, no such
+ * function, or no staging instruction recognised). */
+int rx_isa_check_staging(const void* code, size_t len, const char* arch, const char* kernel, int32_t* violations);
+
 /* Length bucketing and launch shape of rx_match_multi; zero fields mean default. */
 typedef struct {
     int32_t n_edges;    /* bucket edges in use (0 = default ladder 8, 16, 32, ..., 4096) */
@@ -446,7 +472,9 @@ typedef struct {
     int32_t use_graph;      /* 1: replay each slot's step as a hipGraph with updated node parameters */
     int32_t block;          /* strings per work item: 64, 128 or 256 (default 256) */
     int32_t grid;           /* persistent workgroups per step (default 4 per compute unit) */
-    int32_t program_slots;  /* resident programs (default 1024) */
+    int32_t program_slots;  /* resident programs (default 1024; at least `slots`).  One step uses at most
+                               min(64, program_slots / slots) distinct programs, so the steps in flight
+                               never hold every resident slot */
 } rx_server_config;
 
 typedef struct {
@@ -466,7 +494,9 @@ typedef struct rx_server rx_server;
  * budget), RX_EHIP. */
 int rx_server_create(const rx_server_config* cfg, rx_server** out);
 
-/* Drains pending requests, stops the scheduler and frees everything. */
+/* Drains pending requests, stops the scheduler and frees everything.  After a
+ * failed step no further step runs: requests still waiting fail with that
+ * step's status, so every rx_server_wait returns. */
 void rx_server_destroy(rx_server* srv);
 
 /* Submits one request: the expression (as for rx_compile) and n host strings
@@ -493,6 +523,20 @@ int rx_server_reset_stats(rx_server* srv);
 int rx_plain_match(const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx_class* classes, int32_t n_classes,
                    uint32_t flags, const uint8_t* host_bytes, const int64_t* host_offsets, int64_t n,
                    uint8_t* host_out);
+
+/* The same plain path with its resources made once: rx_plain_create makes one
+ * stream and device buffers for requests of at most max_bytes string bytes and
+ * max_strings strings (plus a 1 MiB table buffer); rx_plain_run then does, per
+ * request, exactly compile, upload, copy in, one rx_match launch, copy out,
+ * synchronise -- no allocation on the device and no stream creation.  Same
+ * request arguments as rx_server_submit.  Errors: RX_EINVAL, RX_ETOOBIG (above
+ * the context's capacity), RX_EHIP.  A context is used by one thread at a time. */
+typedef struct rx_plain rx_plain;
+int rx_plain_create(int64_t max_bytes, int64_t max_strings, rx_plain** out);
+int rx_plain_run(rx_plain* ctx, const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx_class* classes,
+                 int32_t n_classes, uint32_t flags, const uint8_t* host_bytes, const int64_t* host_offsets, int64_t n,
+                 uint8_t* host_out);
+void rx_plain_destroy(rx_plain* ctx);
 
 /* Thread-local message of the last failed call on this host thread. */
 const char* rx_last_error(void);

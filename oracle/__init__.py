@@ -69,17 +69,17 @@ def as_ast(ast) -> np.ndarray:
 
 
 def as_classes(classes) -> np.ndarray:
-    """Classes as an (n, 4) uint64 array; accepts byte iterables or 256-bit ints."""
+    """Classes as an (n, 4) uint64 array.  The encoding of each entry comes from its type (as in
+    ``pwpi._class_set``): an int is a 256-bit mask, ``pwpi.Words`` or a numpy uint64 row holds
+    four 64-bit words, any other iterable lists the member bytes."""
+    from .pwpi import _class_set
+
     if isinstance(classes, np.ndarray) and classes.dtype == np.uint64:
         return np.ascontiguousarray(classes.reshape(-1, 4))
     out = np.zeros((max(len(classes), 1), 4), dtype=np.uint64)
     for i, c in enumerate(classes):
-        if isinstance(c, int):
-            for w in range(4):
-                out[i, w] = (c >> (64 * w)) & ((1 << 64) - 1)
-        else:
-            for b in c:
-                out[i, b >> 6] |= np.uint64(1) << np.uint64(b & 63)
+        for b in _class_set(c):
+            out[i, b >> 6] |= np.uint64(1) << np.uint64(b & 63)
     return out
 
 

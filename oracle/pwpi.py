@@ -50,14 +50,38 @@ _PLUSLOOP = 100
 ALL_BYTES = frozenset(range(256))
 
 
+class Words(tuple):
+    """A byte set given as four 64-bit words: byte b is bit (b & 63) of word b >> 6."""
+
+    def __new__(cls, words):
+        words = tuple(int(w) for w in words)
+        if len(words) != 4 or any(not 0 <= w < (1 << 64) for w in words):
+            raise ValueError("a word-encoded class is exactly four 64-bit words")
+        return super().__new__(cls, words)
+
+
 def _class_set(mask) -> frozenset:
-    """A class given as a 256-bit integer, a 4-word list or an iterable of bytes."""
+    """The byte set of a class.  The encoding is taken from the type, never from the values:
+
+    * a Python ``int``: a 256-bit mask (byte b is bit b);
+    * ``Words`` or a numpy ``uint64`` array of shape (4,): four 64-bit words
+      (byte b is bit b & 63 of word b >> 6) -- the layout of the C interface;
+    * any other iterable: the member bytes themselves (each 0..255).
+    """
+    if isinstance(mask, bool):
+        raise TypeError("a class is not a bool")
     if isinstance(mask, int):
+        if not 0 <= mask < (1 << 256):
+            raise ValueError("a 256-bit class mask is out of range")
         return frozenset(b for b in range(256) if (mask >> b) & 1)
-    mask = list(mask)
-    if len(mask) == 4 and any(v > 255 for v in mask):
-        return frozenset(b for b in range(256) if (mask[b >> 6] >> (b & 63)) & 1)
-    return frozenset(mask)
+    dtype = getattr(mask, "dtype", None)
+    if isinstance(mask, Words) or (dtype is not None and str(dtype) == "uint64"):
+        w = Words(list(mask))
+        return frozenset(b for b in range(256) if (w[b >> 6] >> (b & 63)) & 1)
+    members = [int(v) for v in mask]
+    if any(not 0 <= v <= 255 for v in members):
+        raise ValueError("a class given by its members holds bytes 0..255 only")
+    return frozenset(members)
 
 
 def label_of(node, classes):

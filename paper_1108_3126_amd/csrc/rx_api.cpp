@@ -633,6 +633,26 @@ int rx_program_jit_staging(const rx_program* prog, int32_t staged[7]) {
     return RX_OK;
 }
 
+int rx_program_jit_guard(const rx_program* prog, int32_t* ran, int32_t violations[8], int32_t* dropped) {
+    if (!prog || !ran || !violations || !dropped) return fail(RX_EINVAL, "NULL argument");
+    jit_guard(reinterpret_cast<const Program*>(prog), ran, violations, dropped);
+    return RX_OK;
+}
+
+int rx_isa_check_staging(const void* code, size_t len, const char* arch, const char* kernel, int32_t* violations) {
+    RX_GUARD_BEGIN
+    if (!code || !arch || !kernel || !violations) return fail(RX_EINVAL, "NULL argument");
+    std::vector<char> co(static_cast<const char*>(code), static_cast<const char*>(code) + len);
+    int v = 0;
+    std::string example;
+    const int rc = isa_check_agpr_staging(co, arch, kernel, &v, &example);
+    *violations = v;
+    if (rc != 0) return fail(RX_EINVAL, "the check could not run on this code object (code " + std::to_string(rc) + ")");
+    if (v) return fail(RX_OK, "first offending instruction:" + example);
+    return RX_OK;
+    RX_GUARD_END
+}
+
 const char* rx_last_error(void) { return last_error_cstr(); }
 
 int rx_trace_enabled(void) { return trace_enabled() ? 1 : 0; }

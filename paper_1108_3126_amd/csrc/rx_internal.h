@@ -173,6 +173,13 @@ void jit_free(Program* P);
 bool jit_ready(const Program* P, int* n_state, int* n_ops);
 // staged[u] for staging modes u = 0..5 (see rx_program_jit_staging).
 void jit_staging(const Program* P, int32_t staged[7]);
+// Static check of a register-staged kernel in a code object (rx_isa_guard.cpp):
+// *violations = instructions not written by the kernel itself that name an
+// accumulation register.  Returns 0 when the check ran, < 0 when it could not.
+int isa_check_agpr_staging(const std::vector<char>& code, const std::string& arch, const char* kernel,
+                           int* violations, std::string* example);
+// The check's outcome for a program's kernels (see rx_program_jit_guard).
+void jit_guard(const Program* P, int32_t* ran, int32_t violations[8], int32_t* dropped);
 // The staging mode that unroll = 0 selects.
 int jit_default_staging(const Program* P);
 // The skewed kernel's earliest-accept form (kept unless it spills) and its launch.

@@ -861,7 +861,19 @@ struct JitKernel {
     int dev = -1;
     int n_state = 0, n_ops = 0;
     std::string arch;
+    // static check of the register-staged kernels (rx_isa_guard.cpp), per
+    // kernel of kStagedKernels: -1 not checked, else the number of
+    // compiler-made instructions that touch an accumulation register
+    int guard_ran = 0;
+    int guard_violations[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+    int guard_dropped = 0;   // bit k: kernel k was dropped by the check
 };
+
+// The kernels that keep in-flight loads in accumulation registers.
+const char* const kStagedKernels[] = {"rx_sliced_fixed_pf", "rx_sliced_fixed_duo", "rx_sliced_fixed_split",
+                                      "rx_sliced_fixed_skew", "rx_sliced_fixed_skew_w", "rx_sliced_first_skew",
+                                      "rx_sliced_first_skew_w"};
+constexpr int kNumStaged = (int)(sizeof(kStagedKernels) / sizeof(kStagedKernels[0]));
 
 std::string jit_full_source(const Program& P, int* n_state, int* n_ops) {
     std::ostringstream s;
@@ -932,6 +944,18 @@ int jit_compile(Program* P, const char* arch_in) {
     K->arch = arch;
     K->n_state = ns;
     K->n_ops = nops;
+    // Disassemble the staged kernels: each must leave its accumulation
+    // registers to its own loads and LDS writes.
+    K->guard_ran = 1;
+    for (int k = 0; k < kNumStaged; ++k) {
+        int v = 0;
+        if (isa_check_agpr_staging(code, arch, kStagedKernels[k], &v, nullptr) != 0) {
+            K->guard_ran = 0;   // the check could not run: every staged kernel is dropped
+            K->guard_violations[k] = -1;
+        } else {
+            K->guard_violations[k] = v;
+        }
+    }
     if (dev >= 0) {
         hipError_t e = hipModuleLoadData(&K->mod, code.data());
         if (e != hipSuccess) { delete K; return fail(RX_EHIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e)); }
@@ -953,10 +977,17 @@ int jit_compile(Program* P, const char* arch_in) {
         // believes already hold their data; a kernel that spills could move
         // such a register before its load lands.  Those kernels are dropped
         // for this program and the LDS-staged kernel runs instead.
-        for (hipFunction_t* f : {&K->fixed64, &K->duo, &K->split, &K->skew, &skew_w, &K->first, &first_w}) {
+        // Kernels that failed the static check are dropped as well.
+        hipFunction_t* staged[kNumStaged] = {&K->fixed64, &K->duo, &K->split, &K->skew, &skew_w, &K->first, &first_w};
+        for (int k = 0; k < kNumStaged; ++k) {
+            hipFunction_t* f = staged[k];
             int scratch = 1;
             if (hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, *f) != hipSuccess || scratch != 0)
                 *f = nullptr;
+            if (*f && (!K->guard_ran || K->guard_violations[k] != 0)) {
+                *f = nullptr;
+                K->guard_dropped |= 1 << k;
+            }
         }
         K->skew_words = !K->skew && skew_w;
         if (!K->skew) K->skew = skew_w;   // the skewed kernel with single-dword transposer reads
@@ -1001,6 +1032,13 @@ void jit_staging(const Program* P, int32_t staged[7]) {
     staged[4] = K->split ? 1 : 0;
     staged[5] = K->skew ? (K->skew_words ? 2 : 1) : 0;
     staged[6] = K->first ? (K->first_words ? 2 : 1) : 0;
+}
+
+void jit_guard(const Program* P, int32_t* ran, int32_t violations[8], int32_t* dropped) {
+    const JitKernel* K = static_cast<const JitKernel*>(P->jit);
+    *ran = K ? K->guard_ran : 0;
+    *dropped = K ? K->guard_dropped : 0;
+    for (int k = 0; k < 8; ++k) violations[k] = K ? K->guard_violations[k] : -1;
 }
 
 bool jit_first_ready(const Program* P) {

@@ -20,6 +20,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -42,6 +43,8 @@ struct CacheEntry {
     int arena_slot = -1;
     int inflight = 0;          // running steps that read these tables
     uint64_t last_used = 0;
+    int upload_slot = -1;      // the slot whose stream carried the last upload of the tables
+    uint64_t upload_seq = 0;   // the step of that slot which enqueued it
 };
 
 struct Request {
@@ -60,6 +63,9 @@ struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done_ev = nullptr;
     hipEvent_t start_ev = nullptr;
+    hipEvent_t upload_ev = nullptr;   // after the program uploads of the slot's current step
+    uint64_t seq = 0;                 // the step the slot is running
+    bool uploaded = false;            // the current step enqueued uploads
     uint8_t *h_bytes = nullptr, *h_out = nullptr, *h_items = nullptr;
     int64_t* h_offs = nullptr;
     uint8_t *d_bytes = nullptr, *d_out = nullptr, *d_items = nullptr;
@@ -105,6 +111,8 @@ struct Server {
     bool launch_step(Slot& s, std::vector<Request*>& take);
     void complete(Slot& s);
     int ensure_resident(CacheEntry* e, Slot& s);
+    void fail_pending_locked(int rc);
+    int max_step_programs() const;
 };
 
 static int hip_err(hipError_t e, const char* what) {
@@ -126,6 +134,7 @@ int Server::init() {
         hipError_t e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
         if (!e) e = hipEventCreate(&s.done_ev);
         if (!e) e = hipEventCreate(&s.start_ev);
+        if (!e) e = hipEventCreateWithFlags(&s.upload_ev, hipEventDisableTiming);
         if (!e) e = hipHostMalloc((void**)&s.h_bytes, nb, hipHostMallocDefault);
         if (!e) e = hipHostMalloc((void**)&s.h_offs, no, hipHostMallocDefault);
         if (!e) e = hipHostMalloc((void**)&s.h_items, ni, hipHostMallocDefault);
@@ -149,6 +158,7 @@ Server::~Server() {
         step_graph_destroy(s.graph);
         if (s.done_ev) hipEventDestroy(s.done_ev);
         if (s.start_ev) hipEventDestroy(s.start_ev);
+        if (s.upload_ev) hipEventDestroy(s.upload_ev);
         if (s.stream) hipStreamDestroy(s.stream);
         hipHostFree(s.h_bytes);
         hipHostFree(s.h_offs);
@@ -194,13 +204,39 @@ int Server::ensure_resident(CacheEntry* e, Slot& s) {
     uint8_t* dst = d_arena + (int64_t)victim * kArenaSlotBytes;
     if (hipError_t err = hipMemcpyAsync(dst, e->prog->blob.data(), e->prog->blob.size(), hipMemcpyHostToDevice, s.stream))
         return hip_err(err, "program upload");
+    e->upload_slot = (int)(&s - slots.data());
+    e->upload_seq = step_seq;
+    s.uploaded = true;
     return RX_OK;
+}
+
+// Distinct programs one step may use.  With every slot's step holding at most
+// this many arena entries, a step being assembled always finds an entry no
+// running step reads, so ensure_resident never runs out of slots.
+int Server::max_step_programs() const {
+    const int per_slot = cfg.program_slots / std::max(1, cfg.slots);
+    return std::max(1, std::min(kMaxItemProgs, per_slot));
+}
+
+// Fails every request still waiting for a step (the server has stopped or a
+// step failed); their waiters wake up with the status.  Caller holds mu.
+void Server::fail_pending_locked(int rc) {
+    const Clock::time_point now = Clock::now();
+    for (Request* r : pending) {
+        r->status = rc;
+        r->done = true;
+        r->t_done = now;
+    }
+    pending.clear();
+    cv_done.notify_all();
 }
 
 bool Server::launch_step(Slot& s, std::vector<Request*>& take) {
     TraceRange trace_range_("rx_server.step");
     const Clock::time_point t0 = Clock::now();
     ++step_seq;
+    s.seq = step_seq;
+    s.uploaded = false;
     hipEventRecord(s.start_ev, s.stream);
     s.reqs = take;
     s.line0.clear();
@@ -232,6 +268,16 @@ bool Server::launch_step(Slot& s, std::vector<Request*>& take) {
         r->entry->inflight += 1;
         r->entry->last_used = step_seq;
         s.entries.push_back(r->entry);
+        // tables uploaded by a step still running on another slot: this step's
+        // stream waits for that upload (it was enqueued on the other stream)
+        const int us = r->entry->upload_slot;
+        if (pidx == (int)progs.size() - 1 && us >= 0 && &slots[us] != &s && slots[us].busy &&
+            slots[us].seq == r->entry->upload_seq) {
+            if (hipError_t e = hipStreamWaitEvent(s.stream, slots[us].upload_ev, 0)) {
+                rc = hip_err(e, "wait for a program upload");
+                break;
+            }
+        }
         if (!r->bytes.empty()) std::memcpy(s.h_bytes + byte, r->bytes.data(), r->bytes.size());
         for (int64_t i = 0; i < r->n; ++i) s.h_offs[line + i] = r->offsets[i] + byte;
         for (int64_t t = 0; t < r->n; t += cfg.block) {
@@ -247,6 +293,8 @@ bool Server::launch_step(Slot& s, std::vector<Request*>& take) {
         byte += (int64_t)r->bytes.size();
     }
     s.h_offs[line] = byte;
+    if (rc == RX_OK && s.uploaded)
+        if (hipError_t e = hipEventRecord(s.upload_ev, s.stream)) rc = hip_err(e, "record the program uploads");
     reinterpret_cast<int32_t*>(s.h_items)[0] = (int32_t)items;  // item count
     reinterpret_cast<int32_t*>(s.h_items)[1] = 0;               // queue head
     if (rc == RX_OK) {
@@ -286,7 +334,7 @@ bool Server::launch_step(Slot& s, std::vector<Request*>& take) {
         s.entries.clear();
         fatal = rc;
         fatal_msg = last_error_cstr();
-        cv_done.notify_all();
+        fail_pending_locked(rc);
         return false;
     }
     s.busy = true;
@@ -333,6 +381,9 @@ void Server::run() {
         std::vector<Request*> take;
         {
             std::unique_lock<std::mutex> lk(mu);
+            // after a failed step nothing more runs: waiting requests fail at once
+            if (fatal != RX_OK && !pending.empty()) fail_pending_locked(fatal);
+            // on destruction, pending requests still run (drain) unless a step has failed
             if (stop && pending.empty()) {
                 bool any_busy = false;
                 for (Slot& s : slots) any_busy |= s.busy;
@@ -346,7 +397,7 @@ void Server::run() {
                     const bool fresh = std::find(distinct.begin(), distinct.end(), r->entry) == distinct.end();
                     if ((int)take.size() >= cfg.step_requests || ns + r->n > cfg.step_strings ||
                         nb + (int64_t)r->bytes.size() > cfg.step_bytes ||
-                        (fresh && (int)distinct.size() >= kMaxItemProgs))
+                        (fresh && (int)distinct.size() >= max_step_programs()))
                         break;
                     if (fresh) distinct.push_back(r->entry);
                     take.push_back(r);
@@ -398,6 +449,7 @@ int rx_server_create(const rx_server_config* cfg_in, rx_server** out) {
         if (c.hbm_budget <= 0) c.hbm_budget = 2ll << 30;
         if (c.block != 64 && c.block != 128 && c.block != 256) return fail(RX_EINVAL, "block must be 64, 128 or 256");
         if (c.slots > 8) return fail(RX_EINVAL, "at most 8 slots");
+        if (c.program_slots < c.slots) return fail(RX_EINVAL, "program_slots must be at least slots");
         const int64_t max_items = c.step_strings / c.block + c.step_requests + 1;
         const int64_t per_slot = (c.step_bytes + 16) + 8 * (c.step_strings + 1) + kItemHeader +
                                  (int64_t)sizeof(WorkItem) * max_items + c.step_strings;
@@ -622,6 +674,96 @@ int rx_plain_match(const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx
         hipFree(d_offs);
         hipFree(d_out);
         delete P;
+        if (e) return hip_err(e, "plain match");
+        return rc;
+    } catch (const std::bad_alloc&) {
+        return fail(RX_ENOMEM, "out of host memory");
+    } catch (...) {
+        return fail(RX_EINVAL, "internal error");
+    }
+}
+
+// The plain path with its resources made once: one stream and device buffers
+// sized for the largest request, reused by every call.  Per request it does
+// exactly compile, upload, copy in, one launch, copy out, synchronise.
+struct rx_plain {
+    hipStream_t stream = nullptr;
+    void* d_tab = nullptr;
+    size_t tab_cap = 0;
+    void* d_bytes = nullptr;
+    void* d_offs = nullptr;
+    void* d_out = nullptr;
+    int64_t max_bytes = 0, max_strings = 0;
+    std::vector<int64_t> offs;
+};
+
+int rx_plain_create(int64_t max_bytes, int64_t max_strings, rx_plain** out) {
+    try {
+        if (!out || max_bytes < 0 || max_strings < 0) return fail(RX_EINVAL, "bad argument");
+        *out = nullptr;
+        rx_plain* c = new rx_plain;
+        c->max_bytes = max_bytes;
+        c->max_strings = max_strings;
+        c->tab_cap = 1 << 20;
+        c->offs.resize((size_t)max_strings + 1);
+        hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (!e) e = hipMalloc(&c->d_tab, c->tab_cap);
+        if (!e) e = hipMalloc(&c->d_bytes, (size_t)max_bytes + 16);
+        if (!e) e = hipMalloc(&c->d_offs, 8 * (size_t)(max_strings + 1));
+        if (!e) e = hipMalloc(&c->d_out, (size_t)max_strings + 1);
+        if (e) {
+            rx_plain_destroy(c);
+            return hip_err(e, "plain path buffers");
+        }
+        *out = c;
+        return RX_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(RX_ENOMEM, "out of host memory");
+    }
+}
+
+void rx_plain_destroy(rx_plain* c) {
+    if (!c) return;
+    if (c->stream) {
+        hipStreamSynchronize(c->stream);
+        hipStreamDestroy(c->stream);
+    }
+    hipFree(c->d_tab);
+    hipFree(c->d_bytes);
+    hipFree(c->d_offs);
+    hipFree(c->d_out);
+    delete c;
+}
+
+int rx_plain_run(rx_plain* c, const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx_class* classes,
+                 int32_t n_classes, uint32_t flags, const uint8_t* host_bytes, const int64_t* host_offsets, int64_t n,
+                 uint8_t* host_out) {
+    try {
+        if (!c) return fail(RX_EINVAL, "context is NULL");
+        if (n < 0 || (n > 0 && (!host_offsets || !host_out))) return fail(RX_EINVAL, "bad string batch");
+        const int64_t base = n > 0 ? host_offsets[0] : 0;
+        const int64_t nbytes = n > 0 ? host_offsets[n] - base : 0;
+        if (n > c->max_strings || nbytes > c->max_bytes)
+            return fail(RX_ETOOBIG, "request above the context's capacity");
+        if (nbytes > 0 && !host_bytes) return fail(RX_EINVAL, "bytes is NULL");
+        Program* P = nullptr;
+        if (int rc = compile(ast, n_ast, root, classes, n_classes, flags, &P)) return rc;
+        std::unique_ptr<Program> hold(P);
+        if (P->blob.size() > c->tab_cap)
+            return fail(RX_ETOOBIG, "program tables above the context's table buffer");
+        for (int64_t i = 0; i <= n; ++i) c->offs[i] = n > 0 ? host_offsets[i] - base : 0;
+        int rc = rx_program_upload(reinterpret_cast<rx_program*>(P), c->d_tab, c->tab_cap, c->stream);
+        hipError_t e = hipSuccess;
+        if (!rc && nbytes) e = hipMemcpyAsync(c->d_bytes, host_bytes + base, (size_t)nbytes, hipMemcpyHostToDevice,
+                                              c->stream);
+        if (!rc && !e) e = hipMemcpyAsync(c->d_offs, c->offs.data(), 8 * (size_t)(n + 1), hipMemcpyHostToDevice,
+                                          c->stream);
+        if (!rc && !e && n)
+            rc = rx_match(reinterpret_cast<const rx_program*>(P), static_cast<const uint8_t*>(c->d_bytes),
+                          static_cast<const int64_t*>(c->d_offs), n, static_cast<uint8_t*>(c->d_out), c->stream);
+        if (!rc && !e && n) e = hipMemcpyAsync(host_out, c->d_out, (size_t)n, hipMemcpyDeviceToHost, c->stream);
+        const hipError_t es = hipStreamSynchronize(c->stream);
+        if (!e) e = es;
         if (e) return hip_err(e, "plain match");
         return rc;
     } catch (const std::bad_alloc&) {

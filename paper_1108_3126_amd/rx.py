@@ -98,6 +98,9 @@ SIGNATURES = {
     "rx_program_jit_source": (ctypes.c_int, [_VP, ctypes.c_char_p, _SZ, ctypes.POINTER(_SZ)]),
     "rx_program_jit_stats": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "rx_program_jit_staging": (ctypes.c_int, [_VP, ctypes.POINTER(_I32)]),
+    "rx_program_jit_guard": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "rx_isa_check_staging": (ctypes.c_int, [ctypes.c_char_p, _SZ, ctypes.c_char_p, ctypes.c_char_p,
+                                            ctypes.POINTER(_I32)]),
     "rx_match_first": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _VP]),
     "rx_match_first_fixed": (ctypes.c_int, [_VP, _VP, _I64, _I64, _VP, _VP]),
     "rx_program_node_image": (ctypes.c_int, [_VP, _VP, _SZ, ctypes.POINTER(_SZ)]),
@@ -124,6 +127,9 @@ SIGNATURES = {
     "rx_server_stats": (ctypes.c_int, [_VP, ctypes.POINTER(rx_server_counters)]),
     "rx_server_reset_stats": (ctypes.c_int, [_VP]),
     "rx_plain_match": (ctypes.c_int, [_VP, _I32, _I32, _VP, _I32, _U32, _VP, _VP, _I64, _VP]),
+    "rx_plain_create": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(_VP)]),
+    "rx_plain_run": (ctypes.c_int, [_VP, _VP, _I32, _I32, _VP, _I32, _U32, _VP, _VP, _I64, _VP]),
+    "rx_plain_destroy": (None, [_VP]),
     "rx_stream_copy": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
     "rx_last_error": (ctypes.c_char_p, []),
     "rx_version": (ctypes.c_char_p, []),
@@ -173,13 +179,25 @@ def as_classes(classes) -> np.ndarray:
         return np.zeros((0, 4), np.uint64)
     if isinstance(classes, np.ndarray) and classes.dtype == np.uint64:
         return np.ascontiguousarray(classes.reshape(-1, 4))
+    # each entry's encoding comes from its type: an int is a 256-bit mask, a numpy uint64 row is the
+    # four words of rx_class, any other iterable lists member bytes
     out = np.zeros((len(classes), 4), dtype=np.uint64)
     for i, c in enumerate(classes):
-        if isinstance(c, int):
+        if isinstance(c, (int, np.integer)) and not isinstance(c, bool):
+            c = int(c)
+            if not 0 <= c < (1 << 256):
+                raise ValueError("a 256-bit class mask is out of range")
             for w in range(4):
                 out[i, w] = (c >> (64 * w)) & ((1 << 64) - 1)
+        elif isinstance(c, np.ndarray) and c.dtype == np.uint64:
+            if c.size != 4:
+                raise ValueError("a word-encoded class is four uint64 words")
+            out[i] = c.reshape(4)
         else:
             for b in c:
+                b = int(b)
+                if not 0 <= b <= 255:
+                    raise ValueError("class members are bytes 0..255")
                 out[i, b >> 6] |= np.uint64(1) << np.uint64(b & 63)
     return out
 
@@ -270,6 +288,13 @@ class Program:
         st = (ctypes.c_int32 * 7)()
         _check(lib().rx_program_jit_staging(self._h, st))
         return list(st)
+
+    def jit_guard(self):
+        """The static check of the register-staged kernels: {"ran", "violations" (per kernel), "dropped"}."""
+        ran, dropped = ctypes.c_int32(), ctypes.c_int32()
+        v = (ctypes.c_int32 * 8)()
+        _check(lib().rx_program_jit_guard(self._h, ctypes.byref(ran), v, ctypes.byref(dropped)))
+        return {"ran": ran.value, "violations": list(v)[:7], "dropped": dropped.value}
 
     # -- device -----------------------------------------------------------
     def upload(self, device=None, stream=None):
@@ -363,13 +388,18 @@ def match_long(prog: Program, data, length: int = None, chunks: int = 0, out=Non
     """Chunk-parallel matching of one long string data[:length]: a 1-element uint8 tensor (0/1)."""
     import torch
 
-    if prog._dev_buf is None:
-        prog.upload(device=data.device, stream=stream)
-    if data.dtype != torch.uint8 or not data.is_cuda:
-        raise TypeError("data must be a uint8 device tensor")
-    data = data.contiguous()
+    if data.dtype != torch.uint8:
+        raise TypeError("data must be a uint8 tensor")
     if length is None:
         length = data.numel()
+    # checked before anything runs: the kernels read bytes [0, length) of the tensor
+    if not 0 <= int(length) <= data.numel():
+        raise ValueError(f"length {length} outside the data tensor's {data.numel()} bytes")
+    if not data.is_cuda:
+        raise TypeError("data must be a device tensor")
+    if prog._dev_buf is None:
+        prog.upload(device=data.device, stream=stream)
+    data = data.contiguous()
     need = _SZ()
     _check(lib().rx_match_long_workspace(prog.handle, int(length), int(chunks), ctypes.byref(need)))
     work = torch.empty(max(int(need.value), 4), dtype=torch.uint8, device=data.device)
@@ -386,13 +416,18 @@ def match_first_long(prog: Program, data, length: int = None, chunks: int = 0, o
     """Earliest accepting prefix of one long string data[:length], in chunks: a 1-element int64 tensor (-1: none)."""
     import torch
 
-    if prog._dev_buf is None:
-        prog.upload(device=data.device, stream=stream)
-    if data.dtype != torch.uint8 or not data.is_cuda:
-        raise TypeError("data must be a uint8 device tensor")
-    data = data.contiguous()
+    if data.dtype != torch.uint8:
+        raise TypeError("data must be a uint8 tensor")
     if length is None:
         length = data.numel()
+    # checked before anything runs: the kernels read bytes [0, length) of the tensor
+    if not 0 <= int(length) <= data.numel():
+        raise ValueError(f"length {length} outside the data tensor's {data.numel()} bytes")
+    if not data.is_cuda:
+        raise TypeError("data must be a device tensor")
+    if prog._dev_buf is None:
+        prog.upload(device=data.device, stream=stream)
+    data = data.contiguous()
     need = _SZ()
     _check(lib().rx_match_long_workspace(prog.handle, int(length), int(chunks), ctypes.byref(need)))
     work = torch.empty(max(int(need.value), 8), dtype=torch.uint8, device=data.device)

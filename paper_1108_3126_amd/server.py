@@ -87,3 +87,43 @@ def plain_match(prog, data, offsets) -> np.ndarray:
                                       data.ctypes.data if data.size else None, offsets.ctypes.data, n,
                                       out.ctypes.data))
     return out[:n]
+
+
+class PlainContext:
+    """The plain path with its stream and device buffers made once (rx_plain_*): per request it
+    compiles, uploads, copies in, launches once, copies out and synchronises."""
+
+    def __init__(self, max_bytes: int, max_strings: int):
+        h = ctypes.c_void_p()
+        rx._check(rx.lib().rx_plain_create(int(max_bytes), int(max_strings), ctypes.byref(h)))
+        self._h = h
+
+    def match(self, prog, data, offsets) -> np.ndarray:
+        a, c = _ast_classes(prog)
+        data = np.ascontiguousarray(data, dtype=np.uint8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        n = len(offsets) - 1
+        out = np.zeros(max(n, 1), np.uint8)
+        rx._check(rx.lib().rx_plain_run(self._h, a.ctypes.data, len(a), int(prog.root),
+                                        c.ctypes.data if len(c) else None, len(c),
+                                        rx.RX_SEARCH if prog.search else 0,
+                                        data.ctypes.data if data.size else None, offsets.ctypes.data, n,
+                                        out.ctypes.data))
+        return out[:n]
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            rx.lib().rx_plain_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

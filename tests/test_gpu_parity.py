@@ -184,6 +184,17 @@ def test_sliced_single_program(dev):
     staging = p.jit_staging()
     print("sliced single: staging", staging, flush=True)
     assert staging[0] == 5 and staging[5] == 1   # the skewed kernel is kept and is the default
+    # the static check of the register-staged kernels ran on the device's code object, and every
+    # kernel the staging report keeps passed it
+    guard = p.jit_guard()
+    print("sliced single: guard", guard, flush=True)
+    assert guard["ran"] == 1
+    for k, mode in enumerate((1, 3, 4)):
+        if staging[mode] == 1:
+            assert guard["violations"][k] == 0 and not guard["dropped"] >> k & 1
+        if guard["dropped"] >> k & 1:
+            assert staging[mode] == 0
+    assert guard["violations"][3] == 0 and not guard["dropped"] & 8   # the default kernel passed
     want = oracle_match(prog, s)
     print("sliced single: accepted", int(want.sum()), flush=True)
     for v in (rx.VARIANT_SLICED, rx.VARIANT_LANE, rx.VARIANT_WAVE, 0):

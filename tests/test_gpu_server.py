@@ -120,3 +120,34 @@ def test_admission_errors(dev):
         with pytest.raises(rx.RxError):
             srv.wait(12345)
         assert srv.stats()["rejected"] == 1
+
+
+def test_more_distinct_programs_than_resident_slots(dev):
+    """Four resident program slots, two step slots, 24 distinct programs submitted at once: every
+    request completes (a step takes at most program_slots / slots distinct programs) and its bits
+    equal the oracle's; evictions happen."""
+    from paper_1108_3126_amd import server
+
+    reqs = [W.serving_request(5, i, max_strings=200) for i in range(24)]
+    cfg = dict(SMALL, program_slots=4, slots=2)
+    with server.Server(use_graph=True, **cfg) as srv:
+        ids = [srv.submit(p, s.data, s.offsets) for p, s in reqs]
+        got = [srv.wait(r, timeout_us=60_000_000) for r in ids]
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["cache_evictions"] > 0
+    for (p, s), g in zip(reqs, got):
+        idx, want = _oracle_sample(p, s)
+        assert np.array_equal(g[idx], want)
+
+
+def test_plain_context_equals_plain_path(dev, requests):
+    """The preallocated plain path (one stream, buffers made once) gives the plain path's bits."""
+    from paper_1108_3126_amd import rx, server
+
+    with server.PlainContext(16 << 20, 1 << 16) as ctx:
+        for prog, s in requests:
+            assert np.array_equal(ctx.match(prog, s.data, s.offsets), server.plain_match(prog, s.data, s.offsets))
+        big = W.Strings(np.zeros(17 << 20, np.uint8), np.array([0, 17 << 20], np.int64))
+        with pytest.raises(rx.RxError) as ei:
+            ctx.match(requests[0][0], big.data, big.offsets)
+        assert ei.value.code == rx.RX_ETOOBIG

@@ -44,3 +44,18 @@ def test_workspace_rule_wavefront_rows():
     p = rx.compile(big.ast, big.root)
     assert p.info.words > 16
     assert ws(p, 200_000, 0) == expect(p, 100)   # sqrt(200000 / 20) = 100
+
+
+@pytest.mark.parametrize("fn", ["match_long", "match_first_long"])
+def test_length_beyond_the_tensor_is_refused_before_any_launch(fn):
+    # the row kernels read bytes [0, length): a length past the tensor is refused on the host
+    import torch
+
+    prog = W.single_program(1)
+    p = rx.compile(prog.ast, prog.root, prog.classes, True)
+    data = torch.zeros(100, dtype=torch.uint8)
+    for bad in (101, -1, 1 << 40):
+        with pytest.raises(ValueError):
+            getattr(rx, fn)(p, data, bad)
+    with pytest.raises(TypeError):   # a host tensor never reaches a launch either
+        getattr(rx, fn)(p, data, 100)

@@ -316,3 +316,28 @@ def test_planted_oracle_mistakes_are_caught(bug):
             caught = True
             break
     assert caught
+
+
+def test_class_encoding_is_explicit():
+    # bytes 0x40-0x47 as four words: every word is <= 255, which a value-based guess reads as the byte
+    # list {0, 255}; the encoding comes from the type, so both oracles see the same set.
+    words = pwpi.Words([0, 0xFF, 0, 0])
+    assert pwpi._class_set(words) == frozenset(range(0x40, 0x48))
+    assert pwpi._class_set(np.array([0, 0xFF, 0, 0], np.uint64)) == frozenset(range(0x40, 0x48))
+    low = pwpi.Words([0xFF, 0, 0, 0])                      # bytes 0..7
+    assert pwpi._class_set(low) == frozenset(range(8))
+    assert pwpi._class_set([0, 0xFF, 0, 0]) == frozenset({0, 255})   # a plain list holds member bytes
+    assert pwpi._class_set(1 << 0x41) == frozenset({0x41})
+    with pytest.raises(ValueError):
+        pwpi._class_set([256])
+    # one CLASS leaf starred then 'z': the C oracle, the Python PW-pi machine and Python re agree
+    nodes = [(CLASS, 0, 0, -1, -1), (STAR, 0, 0, 0, -1), (BYTE, ord("z"), 0, -1, -1), (CAT, 0, 0, 1, 2)]
+    strings = [b"z", b"@Az", b"GGGz", b"Hz", b"\x00z", b"\x07z", b"\xffz", b"A", b"@@"]
+    for cls, members in ((words, range(0x40, 0x48)), (low, range(8)),
+                         (np.array([[0, 0xFF, 0, 0]], np.uint64), range(0x40, 0x48))):
+        classes = cls if isinstance(cls, np.ndarray) else [cls]
+        want = [int(all(b in members for b in w[:-1]) and w[-1:] == b"z") for w in strings]
+        assert c_oracle(nodes, 3, classes, False, strings).tolist() == want
+        h = pwpi.Heap(nodes, 3, classes)
+        assert [int(pwpi.pwpi_accepts(h, w)) for w in strings] == want
+        assert [int(pwpi.re_accepts(nodes, 3, classes, w)) for w in strings] == want
