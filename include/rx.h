@@ -282,6 +282,18 @@ int rx_match_long(const rx_program* prog, const uint8_t* d_bytes, int64_t length
 int rx_match_first_long(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int32_t chunks, void* d_work,
                         size_t work_bytes, int64_t* d_first, void* stream);
 
+/* rx_match_long for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same result, with the rows held in a static device array of 16 MiB that the
+ * library owns (one per GPU it runs on, kept until the process ends) instead
+ * of a caller workspace.  No hipMalloc, hipFree or allocating call is made.
+ * chunks = 0 takes the default count, lowered if needed until the rows fit the
+ * array; an explicit count whose rows (rx_match_long_workspace) exceed 16 MiB
+ * fails with RX_ETOOBIG.  Calls that overlap on one GPU share the array and
+ * race: serialise them (one stream, or events).  Other errors as rx_match_long. */
+int rx_match_long_noalloc(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int32_t chunks,
+                          uint8_t* d_out, void* stream);
+
 /* The paper's own GPU machine (§8, on the process translation of §7): every
  * node of d[] is a process owned by one thread of a workgroup; stamp vectors
  * c and n (in LDS) hold which processes have a message in the current macro

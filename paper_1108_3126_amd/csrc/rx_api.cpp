@@ -240,24 +240,14 @@ int rx_match_long_workspace(const rx_program* prog, int64_t length, int32_t chun
     RX_GUARD_END
 }
 
-int rx_match_long(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int32_t chunks, void* d_work,
-                  size_t work_bytes, uint8_t* d_out, void* stream) {
-    TraceRange trace_range_("rx_match_long");
-    RX_GUARD_BEGIN
-    const Program* P = reinterpret_cast<const Program*>(prog);
-    if (!P) return fail(RX_EINVAL, "program is NULL");
-    if (length < 0 || chunks < 0) return fail(RX_EINVAL, "negative length or chunk count");
-    if (!d_out || !d_work || (length > 0 && !d_bytes)) return fail(RX_EINVAL, "NULL device buffer");
-    if (!P->dev) return fail(RX_ENOTUPLOADED, "program has not been uploaded (rx_program_upload)");
-    if (P->W > kWaveMaxWords) return fail(RX_ETOOBIG, "the wavefront kernel holds sets of at most 128 words");
-    int64_t C, cl;
-    long_chunks(P, length, chunks, &C, &cl);
-    const size_t need = long_rows_bytes(P, C);
-    if (work_bytes < need)
-        return fail(RX_EINVAL, "workspace holds " + std::to_string(work_bytes) + " bytes; this run needs " +
-                                   std::to_string(need) + " (rx_match_long_workspace)");
+namespace {
+// The two launches of a chunk-parallel run over C chunks of cl bytes, with the
+// rows in d_work (long_rows_bytes(P, C) bytes; every row is written before it
+// is read, so the workspace needs no clearing).
+int match_long_run(const Program* P, const uint8_t* d_bytes, int64_t length, int64_t C, int64_t cl, void* d_work,
+                   uint8_t* d_out, void* stream) {
     LaunchArgs a;
-    const int64_t rows = 1 + (C - 1) * (int64_t)(P->L + 1);
+    const int64_t rows = long_rows(P, C);
     if (int rc = make_launch_args(P, d_bytes ? d_bytes : static_cast<const uint8_t*>(d_work),
                                   static_cast<const int64_t*>(d_work), rows, d_out, stream, &a))
         return rc;
@@ -272,6 +262,56 @@ int rx_match_long(const rx_program* prog, const uint8_t* d_bytes, int64_t length
     e = launch_compose(a.rows_out, C, P->L + 1, P->W, P->L, P->suffix_any ? 1 : 0, d_out, stream);
     if (e) return hip_fail(e, "kernel launch (composition)");
     return RX_OK;
+}
+
+int check_long_args(const Program* P, const uint8_t* d_bytes, int64_t length, int32_t chunks, const void* d_out) {
+    if (!P) return fail(RX_EINVAL, "program is NULL");
+    if (length < 0 || chunks < 0) return fail(RX_EINVAL, "negative length or chunk count");
+    if (!d_out || (length > 0 && !d_bytes)) return fail(RX_EINVAL, "NULL device buffer");
+    if (!P->dev) return fail(RX_ENOTUPLOADED, "program has not been uploaded (rx_program_upload)");
+    if (P->W > kWaveMaxWords) return fail(RX_ETOOBIG, "the wavefront kernel holds sets of at most 128 words");
+    return RX_OK;
+}
+}  // namespace
+
+int rx_match_long(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int32_t chunks, void* d_work,
+                  size_t work_bytes, uint8_t* d_out, void* stream) {
+    TraceRange trace_range_("rx_match_long");
+    RX_GUARD_BEGIN
+    const Program* P = reinterpret_cast<const Program*>(prog);
+    if (int rc = check_long_args(P, d_bytes, length, chunks, d_out)) return rc;
+    if (!d_work) return fail(RX_EINVAL, "NULL device buffer");
+    int64_t C, cl;
+    long_chunks(P, length, chunks, &C, &cl);
+    const size_t need = long_rows_bytes(P, C);
+    if (work_bytes < need)
+        return fail(RX_EINVAL, "workspace holds " + std::to_string(work_bytes) + " bytes; this run needs " +
+                                   std::to_string(need) + " (rx_match_long_workspace)");
+    return match_long_run(P, d_bytes, length, C, cl, d_work, d_out, stream);
+    RX_GUARD_END
+}
+
+int rx_match_long_noalloc(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int32_t chunks,
+                          uint8_t* d_out, void* stream) {
+    TraceRange trace_range_("rx_match_long_noalloc");
+    RX_GUARD_BEGIN
+    const Program* P = reinterpret_cast<const Program*>(prog);
+    if (int rc = check_long_args(P, d_bytes, length, chunks, d_out)) return rc;
+    int64_t C, cl;
+    long_chunks(P, length, chunks, &C, &cl);
+    if (long_rows_bytes(P, C) > kLongScratchBytes) {
+        if (chunks > 0)
+            return fail(RX_ETOOBIG, std::to_string(chunks) + " chunks need " + std::to_string(long_rows_bytes(P, C)) +
+                                        " bytes of rows; the static workspace holds " +
+                                        std::to_string(kLongScratchBytes));
+        // the default count, lowered until the rows fit the static workspace
+        while (C > 1 && long_rows_bytes(P, C) > kLongScratchBytes) long_chunks(P, length, (int32_t)(C - 1), &C, &cl);
+        if (long_rows_bytes(P, C) > kLongScratchBytes)
+            return fail(RX_ETOOBIG, "one chunk's rows exceed the static workspace");
+    }
+    void* work = nullptr;
+    if (int e = long_scratch(&work)) return hip_fail(e, "device address of the static workspace");
+    return match_long_run(P, d_bytes, length, C, cl, work, d_out, stream);
     RX_GUARD_END
 }
 

@@ -190,6 +190,11 @@ int launch_sliced_first(const Program* P, const uint8_t* bytes, int64_t length, 
 void node_image(const Program* P, std::vector<uint8_t>& img);
 int launch_nodes(const void* image, int32_t m, const uint8_t* bytes, const int64_t* offsets, int64_t stride, int64_t n,
                  uint8_t* out, void* stream);
+// The allocation-free chunk-parallel entry point's workspace: a static device
+// array in rx_kernels.hip (one per GPU, held until the process ends).
+constexpr size_t kLongScratchBytes = (size_t)16 << 20;
+// Its device address on the current device (looked up once per device).
+int long_scratch(void** ptr);
 // first[i] = value for i < n (a fill kernel, no memset)
 int launch_fill_i64(int64_t* first, int64_t n, int64_t value, void* stream);
 int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,

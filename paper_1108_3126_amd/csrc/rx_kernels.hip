@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
+#include <unordered_map>
 
 #include "rx_internal.h"
 
@@ -565,6 +567,31 @@ int launch_fill_i64(int64_t* p, int64_t n, int64_t v, void* stream) {
 }
 
 const char* hip_error_string(int err) { return hipGetErrorString((hipError_t)err); }
+
+// Workspace of rx_match_long_noalloc: a file-scope device array, so the entry
+// point allocates nothing.  In host code `scratch` only stands in for the
+// symbol; its device address on each GPU comes from hipGetSymbolAddress, taken
+// once per device with that device current, and only that address reaches a
+// kernel.  Every call on a GPU shares the GPU's copy: calls that overlap on
+// one GPU race.
+static __device__ __align__(256) unsigned char scratch[kLongScratchBytes];
+
+int long_scratch(void** ptr) {
+    static std::mutex mu;
+    static std::unordered_map<int, void*> by_device;
+    int dev = -1;
+    if (hipError_t e = hipGetDevice(&dev)) return (int)e;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = by_device.find(dev);
+    if (it == by_device.end()) {
+        void* p = nullptr;
+        if (hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) return (int)e;
+        if (!p) return (int)hipErrorInvalidSymbol;
+        it = by_device.emplace(dev, p).first;
+    }
+    *ptr = it->second;
+    return 0;
+}
 
 int hip_current_device(int* dev) { return (int)hipGetDevice(dev); }
 

@@ -108,6 +108,7 @@ SIGNATURES = {
     "rx_trace_enabled": (ctypes.c_int, []),
     "rx_match_first_long": (ctypes.c_int, [_VP, _VP, _I64, _I32, _VP, _SZ, _VP, _VP]),
     "rx_match_long": (ctypes.c_int, [_VP, _VP, _I64, _I32, _VP, _SZ, _VP, _VP]),
+    "rx_match_long_noalloc": (ctypes.c_int, [_VP, _VP, _I64, _I32, _VP, _VP]),
     "rx_match_nodes": (ctypes.c_int, [_VP, _VP, _VP, _VP, _I64, _VP, _VP]),
     "rx_parse": (ctypes.c_int, [ctypes.c_char_p, _SZ, _VP, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _VP, _I32,
                                 ctypes.POINTER(_I32)]),
