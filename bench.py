@@ -297,27 +297,41 @@ def run_multi(args, torch, dev):
     d, o = torch.from_numpy(lines.data).to(dev), torch.from_numpy(lines.offsets).to(dev)
     cfg, tinfo = autotune.tune_multi(ps, d, o, budget_runs=40, use_cache=False)
     log(f"multi tuned: {tinfo}")
-    out = rx.match_multi(ps, d, o, config=cfg)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(3):
-        rx.match_multi(ps, d, o, out=out, config=cfg)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / 3
-    got = out.cpu().numpy()
+
+    def timed(config, reps=3):
+        res = rx.match_multi(ps, d, o, config=config)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            rx.match_multi(ps, d, o, out=res, config=config)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, res.cpu().numpy()
+
+    ms_table, got_table = timed(cfg)
+    # plane form: each program's bit-sliced circuit over length-sorted slabs
+    j0 = time.time()
+    for p in ps:
+        p.jit_planes()
+    jit_s = time.time() - j0
+    pcfg = rx.multi_config(form=rx.FORM_PLANES, max_bytes=int(lines.offsets[-1]))
+    ms_planes, got = timed(pcfg)
+    log(f"multi: table form {ms_table:.3f} ms, plane form {ms_planes:.3f} ms (circuits compiled in {jit_s:.1f} s)")
+    ok = bool(np.array_equal(got, got_table))
     rng = np.random.default_rng(7)
-    ok = True
     for k, pr in enumerate(progs):
         idx = np.unique(rng.choice(lines.n, size=150, replace=False)).astype(np.int64)
         want = oracle.match(pr.ast, pr.root, pr.classes, True, lines.data, lines.offsets, index=idx)
         ok = ok and bool(np.array_equal(got[k][idx], want))
     nbytes = int(lines.offsets[-1])
+    ms = ms_planes
     return {"metric": "unique input GB/s, all programs per line", "workload": "multi: 16 programs x 4M lines",
-            "ms": round(ms, 3), "input_GBs": round(nbytes / (ms * 1e-3) / 1e9, 2),
+            "form": "planes", "ms": round(ms, 3), "input_GBs": round(nbytes / (ms * 1e-3) / 1e9, 2),
             "byte_program_steps_per_s": round(nbytes * len(progs) / (ms * 1e-3), 0),
-            "accepted_per_program": got.sum(axis=1).tolist(), "config": tinfo, "bit_exact_sample": ok}
+            "table_form_ms": round(ms_table, 3), "speedup_vs_table": round(ms_table / ms, 2),
+            "accepted_per_program": got.sum(axis=1).tolist(), "table_config": tinfo,
+            "bit_exact_sample": ok, "planes_equal_table": bool(np.array_equal(got, got_table))}
 
 
 def run_pathological(args, torch, dev):

@@ -396,6 +396,23 @@ int rx_program_jit_staging(const rx_program* prog, int32_t staged[7]);
  * shows what runs instead).  Errors: RX_EINVAL (NULL arguments). */
 int rx_program_jit_guard(const rx_program* prog, int32_t* ran, int32_t violations[8], int32_t* dropped);
 
+/* Generates and compiles the plane-form circuit of the program (its own small
+ * module: the per-node processes of §7 as boolean signals over 32 strings per
+ * word, fed precomputed bit planes), for rx_match_multi with RX_FORM_PLANES.
+ * arch as for rx_program_jit.  Without a device the source is only compiled.
+ * Programs keep their leaf states in registers where they fit; the device
+ * compiler spills the rest.  Errors: RX_EJIT, RX_ETOOBIG (more than 1024
+ * state words), RX_EHIP. */
+int rx_program_jit_planes(rx_program* prog, const char* arch);
+
+/* The plane-form circuit's generated source, as rx_program_jit_source. */
+int rx_program_jit_planes_source(const rx_program* prog, char* buf, size_t cap, size_t* len);
+
+/* ready = 1 when the plane-form circuit is loaded; state_words as in
+ * rx_program_jit_stats; spill_bytes = per-lane private memory the device
+ * compiler gave the kernel (register spills; 0 when everything fits). */
+int rx_program_planes_info(const rx_program* prog, int32_t* ready, int32_t* state_words, int32_t* spill_bytes);
+
 /* The same check on any code object (an AMDGPU ELF of len bytes, owned by the
  * caller) for the function `kernel` compiled for `arch` (e.g. "gfx950"):
  * *violations = instructions that name an accumulation register other than
@@ -411,10 +428,17 @@ typedef struct {
     int32_t edges[15];  /* ascending; bucket b holds lengths in (edges[b-1], edges[b]], the last one the rest */
     int32_t block;      /* strings per work item = threads per workgroup: 64, 128 or 256 (default 256) */
     int32_t grid;       /* persistent workgroups (default 4 per compute unit) */
+    int32_t form;       /* RX_FORM_TABLE (0, default) or RX_FORM_PLANES (see rx_match_multi) */
+    int32_t reserved;   /* 0 */
+    int64_t max_bytes;  /* RX_FORM_PLANES: at least the total bytes of all strings (e.g. the size of the
+                           bytes buffer); sizes the workspace */
 } rx_multi_config;
 
+enum { RX_FORM_TABLE = 0, RX_FORM_PLANES = 1 };
+
 /* Device workspace rx_match_multi needs for n strings and n_progs programs
- * (bytes), or a negative RX_E* code. */
+ * (bytes), or a negative RX_E* code.  For RX_FORM_PLANES it grows with
+ * cfg->max_bytes: about 9/8 of it for the bit planes plus 4 bytes per string. */
 int64_t rx_match_multi_workspace(int64_t n, int32_t n_progs, const rx_multi_config* cfg);
 
 /*
@@ -430,6 +454,20 @@ int64_t rx_match_multi_workspace(int64_t n, int32_t n_progs, const rx_multi_conf
  * most 64.  Allocates nothing; asynchronous on `stream`.  Results do not
  * depend on the bucketing or launch shape.
  * Errors: RX_EINVAL, RX_ETOOBIG, RX_ENOTUPLOADED, RX_EHIP.
+ */
+/*
+ * RX_FORM_PLANES (the bit-sliced circuit for strings of any length, §7):
+ * strings are counting-sorted by length on the device (lengths below 8191
+ * exactly; longer strings run in table form), cut into slabs of 2048
+ * consecutive sorted strings, and every slab's bytes are gathered and
+ * transposed once into bit planes (32 strings per word, plus one word per
+ * position marking the strings that still have bytes).  Each program's
+ * plane-form circuit (rx_program_jit_planes) then runs over all slabs, one
+ * wavefront per slab, and keeps each string's accept bit as of its last byte.
+ * Every program must have that circuit loaded on the current device;
+ * cfg->max_bytes must be at least the total length of the strings (with a
+ * smaller bound the slabs are skipped and their results are unspecified; no
+ * memory outside the workspace is touched).
  */
 int rx_match_multi(const rx_program* const* progs, int32_t n_progs, const uint8_t* d_bytes,
                    const int64_t* d_offsets, int64_t n, uint8_t* d_out, void* d_work, size_t work_bytes,

@@ -91,7 +91,10 @@ int rx_compile(const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx_cla
 void rx_program_free(rx_program* prog) {
     try {
         Program* P = reinterpret_cast<Program*>(prog);
-        if (P) jit_free(P);
+        if (P) {
+            jit_free(P);
+            jit_planes_free(P);
+        }
         delete P;
     } catch (...) {
     }
@@ -553,9 +556,60 @@ int64_t rx_match_multi_workspace(int64_t n, int32_t n_progs, const rx_multi_conf
     block = cfg && cfg->block ? cfg->block : 256;
     (void)edges;
     (void)grid;
+    if (cfg && cfg->form == RX_FORM_PLANES) {
+        if (cfg->max_bytes < 0) return fail(RX_EINVAL, "negative max_bytes");
+        return plane_workspace_bytes(n, cfg->max_bytes, n_progs > 0 ? n_progs : 1, block);
+    }
     return multi_workspace_bytes(n, n_progs > 0 ? n_progs : 1, ne + 1, block);
     RX_GUARD_END
 }
+
+namespace {
+// rx_match_multi in plane form: every program's plane-form circuit over slabs
+// of length-sorted strings; strings of kSortBins - 1 bytes or more in table form.
+int match_multi_planes(const rx_program* const* progs, int32_t n_progs, const uint8_t* d_bytes,
+                       const int64_t* d_offsets, int64_t n, uint8_t* d_out, void* d_work, size_t work_bytes,
+                       const rx_multi_config& cfg, const MultiArgs& shape, void* stream) {
+    if (cfg.max_bytes < 0) return fail(RX_EINVAL, "negative max_bytes");
+    const int64_t need = plane_workspace_bytes(n, cfg.max_bytes, n_progs, shape.block_lines);
+    if ((int64_t)work_bytes < need)
+        return fail(RX_ETOOBIG, "workspace holds " + std::to_string(work_bytes) + " bytes; need " + std::to_string(need));
+    PlaneMultiArgs m;
+    for (int i = 0; i < n_progs; ++i) {
+        const Program* P = reinterpret_cast<const Program*>(progs[i]);
+        if (!P) return fail(RX_EINVAL, "program " + std::to_string(i) + " is NULL");
+        if (!P->dev) return fail(RX_ENOTUPLOADED, "program " + std::to_string(i) + " has not been uploaded");
+        if (P->W > kLaneMaxWords) return fail(RX_ETOOBIG, "program " + std::to_string(i) + " holds more than 16 words");
+        if (!jit_planes_ready(P, nullptr, nullptr))
+            return fail(RX_EINVAL, "program " + std::to_string(i) + " has no plane-form circuit (rx_program_jit_planes)");
+        const uint8_t* base = static_cast<const uint8_t*>(P->dev);
+        m.progs[i] = P;
+        m.descs[i].first = reinterpret_cast<const uint32_t*>(base + P->layout.first);
+        m.descs[i].follow = reinterpret_cast<const uint32_t*>(base + P->layout.follow);
+        m.descs[i].bytemask = reinterpret_cast<const uint32_t*>(base + P->layout.bytemask);
+        m.descs[i].L = P->L;
+        m.descs[i].W = P->W;
+        m.descs[i].suffix_any = P->suffix_any ? 1 : 0;
+        m.descs[i].pad = 0;
+    }
+    m.n_progs = n_progs;
+    m.block_lines = shape.block_lines;
+    m.item_grid = shape.grid;
+    int cus = 0;
+    if (hip_cu_count(&cus) || cus <= 0) cus = 256;
+    m.plane_grid = 4 * cus;
+    m.bytes = d_bytes;
+    m.offsets = d_offsets;
+    m.n = n;
+    m.max_bytes = cfg.max_bytes;
+    m.out = d_out;
+    m.work = d_work;
+    m.stream = stream;
+    if (n == 0) return RX_OK;
+    if (int e = launch_planes_multi(m)) return hip_fail(e, "plane-form launch");
+    return RX_OK;
+}
+}  // namespace
 
 int rx_match_multi(const rx_program* const* progs, int32_t n_progs, const uint8_t* d_bytes,
                    const int64_t* d_offsets, int64_t n, uint8_t* d_out, void* d_work, size_t work_bytes,
@@ -570,6 +624,9 @@ int rx_match_multi(const rx_program* const* progs, int32_t n_progs, const uint8_
     if (!d_work || (reinterpret_cast<uintptr_t>(d_work) & 255)) return fail(RX_EINVAL, "workspace must be 256-byte aligned");
     MultiArgs m;
     if (int rc = multi_shape(cfg, m.edges, &m.n_edges, &m.block_lines, &m.grid)) return rc;
+    if (cfg && cfg->form != RX_FORM_TABLE && cfg->form != RX_FORM_PLANES) return fail(RX_EINVAL, "unknown form");
+    if (cfg && cfg->form == RX_FORM_PLANES) return match_multi_planes(progs, n_progs, d_bytes, d_offsets, n, d_out,
+                                                                     d_work, work_bytes, *cfg, m, stream);
     const int64_t need = multi_workspace_bytes(n, n_progs, m.n_edges + 1, m.block_lines);
     if ((int64_t)work_bytes < need)
         return fail(RX_ETOOBIG, "workspace holds " + std::to_string(work_bytes) + " bytes; need " + std::to_string(need));
@@ -657,6 +714,20 @@ int rx_program_jit_source(const rx_program* prog, char* buf, size_t cap, size_t*
     RX_GUARD_END
 }
 
+int rx_program_jit_planes_source(const rx_program* prog, char* buf, size_t cap, size_t* len) {
+    RX_GUARD_BEGIN
+    if (!prog) return fail(RX_EINVAL, "program is NULL");
+    const std::string s = jit_planes_source(*reinterpret_cast<const Program*>(prog), nullptr);
+    if (len) *len = s.size();
+    if (buf && cap) {
+        const size_t k = s.size() < cap - 1 ? s.size() : cap - 1;
+        std::memcpy(buf, s.data(), k);
+        buf[k] = 0;
+    }
+    return RX_OK;
+    RX_GUARD_END
+}
+
 int rx_program_jit_stats(const rx_program* prog, int32_t* ready, int32_t* state_words, int32_t* ops) {
     if (!prog) return fail(RX_EINVAL, "program is NULL");
     int ns = 0, no = 0;
@@ -670,6 +741,26 @@ int rx_program_jit_stats(const rx_program* prog, int32_t* ready, int32_t* state_
 int rx_program_jit_staging(const rx_program* prog, int32_t staged[7]) {
     if (!prog || !staged) return fail(RX_EINVAL, "NULL argument");
     jit_staging(reinterpret_cast<const Program*>(prog), staged);
+    return RX_OK;
+}
+
+int rx_program_jit_planes(rx_program* prog, const char* arch) {
+    TraceRange trace_range_("rx_program_jit_planes");
+    RX_GUARD_BEGIN
+    if (!prog) return fail(RX_EINVAL, "program is NULL");
+    int rc = jit_compile_planes(reinterpret_cast<Program*>(prog), arch);
+    if (rc == RX_OK) clear_error();
+    return rc;
+    RX_GUARD_END
+}
+
+int rx_program_planes_info(const rx_program* prog, int32_t* ready, int32_t* state_words, int32_t* spill_bytes) {
+    if (!prog) return fail(RX_EINVAL, "program is NULL");
+    int ns = 0, sc = 0;
+    const bool r = jit_planes_ready(reinterpret_cast<const Program*>(prog), &ns, &sc);
+    if (ready) *ready = r ? 1 : 0;
+    if (state_words) *state_words = ns;
+    if (spill_bytes) *spill_bytes = sc;
     return RX_OK;
 }
 

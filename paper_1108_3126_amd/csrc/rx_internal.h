@@ -16,6 +16,7 @@ constexpr int kMaxNodes = 1 << 20;
 constexpr int kLaneMaxWords = 16;       // one-lane-per-string kernel limit (L <= 511)
 constexpr int kWaveMaxWords = 128;      // wavefront kernel limit: lane j owns words j and j+64
 constexpr int kJitMaxState = 160;       // sliced circuit: leaf state words kept in registers
+constexpr int kJitPlanesMaxState = 1024; // plane-form circuit: the device compiler spills what registers cannot hold
 constexpr int kNodesMaxNodes = 8191;    // node-per-thread machine: two stamp vectors of m + 1 in LDS
 
 // Device table layout (all offsets in bytes from the start of the uploaded
@@ -48,6 +49,8 @@ struct Program {
     int dev_id = -1;
     // run-time generated kernel for the bit-sliced circuit (may be null)
     void* jit = nullptr;
+    // run-time generated plane-form circuit for strings of any length (may be null)
+    void* jit_planes = nullptr;
 };
 
 // batched matching (rx_multi.hip)
@@ -112,6 +115,28 @@ int step_graph_launch(StepGraph** g, const StepDesc& d, void* stream);
 void step_graph_destroy(StepGraph* g);
 
 int64_t multi_workspace_bytes(int64_t n, int32_t n_progs, int32_t n_buckets, int32_t block_lines);
+
+// plane form of batched matching (rx_multi.hip): exact-length sort, slabs of
+// 2048 strings, bit planes gathered once, every program's circuit over them
+constexpr int kSortBins = 8192;      // lengths 0 .. 8190 sort exactly; longer strings run in table form
+struct PlaneMultiArgs {
+    const Program* progs[kMaxItemProgs];   // each with a loaded plane-form circuit
+    ProgDesc descs[kMaxItemProgs];         // device tables (strings too long for a slab)
+    int32_t n_progs;
+    int32_t block_lines;                   // table-form item size
+    int32_t plane_grid, item_grid;
+    const uint8_t* bytes;
+    const int64_t* offsets;
+    int64_t n;
+    int64_t max_bytes;                     // upper bound of the total string bytes
+    uint8_t* out;
+    void* work;
+    void* stream;
+};
+int64_t plane_max_slabs(int64_t n);
+int64_t plane_tick_cap(int64_t n, int64_t max_bytes);
+int64_t plane_workspace_bytes(int64_t n, int64_t max_bytes, int32_t n_progs, int32_t block_lines);
+int launch_planes_multi(const PlaneMultiArgs& m);
 int launch_multi(const MultiArgs& m);
 int launch_items(const ItemsArgs& m);
 
@@ -173,6 +198,14 @@ void jit_free(Program* P);
 bool jit_ready(const Program* P, int* n_state, int* n_ops);
 // staged[u] for staging modes u = 0..5 (see rx_program_jit_staging).
 void jit_staging(const Program* P, int32_t staged[7]);
+// Plane-form circuit (rx_jit.cpp): its own small module per program.
+std::string jit_planes_source(const Program& P, int* n_state);
+int jit_compile_planes(Program* P, const char* arch);
+void jit_planes_free(Program* P);
+bool jit_planes_ready(const Program* P, int* n_state, int* scratch);
+// One wavefront per slab (grid max_slabs; slabs beyond counts[0] exit at once).
+int launch_sliced_planes(const Program* P, const uint32_t* planes, const int64_t* slab_tick, const int32_t* sorted,
+                         const int64_t* counts, int64_t max_slabs, uint8_t* out, void* stream);
 // Static check of a register-staged kernel in a code object (rx_isa_guard.cpp):
 // *violations = instructions not written by the kernel itself that name an
 // accumulation register.  Returns 0 when the check ran, < 0 when it could not.

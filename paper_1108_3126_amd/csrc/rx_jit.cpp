@@ -848,6 +848,80 @@ extern "C" __global__ __launch_bounds__(64, 1) void rx_sliced_fixed_pf(const uns
 }
 )RX";
 
+// Plane form: the circuit driven by bit planes that a separate kernel has
+// already gathered and transposed (rx_multi.hip), for strings of any length.
+// A slab is 2048 strings (lane l holds strings 64 j + l in bit j); tick t of a
+// slab is positions 4t .. 4t+3 as 36 words per lane: w[8i + b] = bit plane b
+// of position 4t + i, w[32 + i] = the strings whose length exceeds 4t + i.
+// In memory a tick is nine groups of four words, group q of lane l at
+// u32 index ((t * 9 + q) * 64 + l) * 4.  After each step a string's accept
+// bit is taken only while the string still has bytes, so it holds the value
+// after the string's last byte (the start value for the empty string).
+const char* kPlanesSource = R"RX(
+__device__ __forceinline__ void rx_planes_tick(u32 (&s)[RX_NS], u32& acc, u32& accf, const u32 (&w)[36]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        rx_step(s, acc, w[8 * i], w[8 * i + 1], w[8 * i + 2], w[8 * i + 3], w[8 * i + 4], w[8 * i + 5],
+                w[8 * i + 6], w[8 * i + 7]);
+        const u32 v = w[32 + i];
+        accf = (acc & v) | (accf & ~v);
+    }
+}
+// ---- device kernel ----
+typedef unsigned int rx_pv4 __attribute__((ext_vector_type(4)));
+// One wavefront per slab, longest slabs first.  slab_tick[s] .. slab_tick[s+1]
+// are the slab's ticks in `planes`; sorted[s * 2048 + k] is the string the
+// slab's k-th entry stands for; counts[0] is the number of strings in slabs.
+extern "C" __global__ __launch_bounds__(64) void rx_sliced_planes(const u32* __restrict__ planes,
+        const long long* __restrict__ slab_tick, const int* __restrict__ sorted, const long long* __restrict__ counts,
+        unsigned char* __restrict__ out) {
+    const long long n_sliced = counts[0];
+    const long long s = (n_sliced + 2047) / 2048 - 1 - (long long)blockIdx.x;
+    if (s < 0) return;
+    const int lane = threadIdx.x;
+    const long long t0 = slab_tick[s], T = slab_tick[s + 1] - t0;
+    const rx_pv4* p = reinterpret_cast<const rx_pv4*>(planes) + t0 * (9 * 64) + lane;
+    u32 st[RX_NS];
+    u32 acc;
+    rx_init(st, acc);
+    u32 accf = acc;
+    rx_pv4 cur[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) cur[q] = T > 0 ? p[q * 64] : rx_pv4{0u, 0u, 0u, 0u};
+    for (long long t = 0; t < T; ++t) {
+        // the next tick streams in while this one runs
+        const rx_pv4* pn = p + (t + 1 < T ? t + 1 : t) * (9 * 64);
+        rx_pv4 nxt[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) nxt[q] = pn[q * 64];
+        u32 w[36];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            w[4 * q] = cur[q].x;
+            w[4 * q + 1] = cur[q].y;
+            w[4 * q + 2] = cur[q].z;
+            w[4 * q + 3] = cur[q].w;
+        }
+        rx_planes_tick(st, acc, accf, w);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) cur[q] = nxt[q];
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        const long long k = s * 2048 + j * 64 + lane;
+        if (k < n_sliced) out[sorted[k]] = (unsigned char)((accf >> j) & 1u);
+    }
+}
+)RX";
+
+struct JitPlanes {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+    int dev = -1;
+    int n_state = 0;
+    int scratch = 0;   // private bytes per lane (register spills the compiler chose)
+};
+
 struct JitKernel {
     hipModule_t mod = nullptr;
     hipFunction_t fixed = nullptr;
@@ -893,22 +967,22 @@ std::unordered_map<std::string, std::vector<char>> g_code_cache;
 constexpr size_t kCodeCacheEntries = 64;
 }  // namespace
 
-int jit_compile(Program* P, const char* arch_in) {
-    int ns = 0, nops = 0;
-    const std::string src = jit_full_source(*P, &ns, &nops);
-    if (ns > kJitMaxState)
-        return fail(RX_ETOOBIG, "the bit-sliced circuit keeps at most " + std::to_string(kJitMaxState) +
-                                    " state words in registers; this program needs " + std::to_string(ns));
-    std::string arch;
-    int dev = -1;
+// The device's architecture name (arch_in when given: compile only, dev = -1).
+int jit_target(const char* arch_in, std::string* arch, int* dev) {
+    *dev = -1;
     if (arch_in && *arch_in) {
-        arch = arch_in;
-    } else {
-        if (hipGetDevice(&dev) != hipSuccess) return fail(RX_EHIP, "hipGetDevice failed");
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(RX_EHIP, "hipGetDeviceProperties failed");
-        arch = prop.gcnArchName;
+        *arch = arch_in;
+        return RX_OK;
     }
+    if (hipGetDevice(dev) != hipSuccess) return fail(RX_EHIP, "hipGetDevice failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, *dev) != hipSuccess) return fail(RX_EHIP, "hipGetDeviceProperties failed");
+    *arch = prop.gcnArchName;
+    return RX_OK;
+}
+
+// Compiles `src` for `arch` with hiprtc (or takes the cached code object).
+int jit_code(const std::string& src, const std::string& arch, std::vector<char>* out) {
     const std::string key = arch + '\n' + src;
     std::vector<char> code;
     {
@@ -940,6 +1014,88 @@ int jit_compile(Program* P, const char* arch_in) {
         if (g_code_cache.size() >= kCodeCacheEntries) g_code_cache.clear();
         g_code_cache.emplace(key, code);
     }
+    *out = std::move(code);
+    return RX_OK;
+}
+
+std::string jit_planes_source(const Program& P, int* n_state) {
+    std::ostringstream s;
+    s << "typedef unsigned int u32;\n";
+    s << jit_step_source(P, n_state, nullptr);
+    s << kPlanesSource;
+    return s.str();
+}
+
+int jit_compile_planes(Program* P, const char* arch_in) {
+    int ns = 0;
+    const std::string src = jit_planes_source(*P, &ns);
+    if (ns > kJitPlanesMaxState)
+        return fail(RX_ETOOBIG, "the plane-form circuit keeps at most " + std::to_string(kJitPlanesMaxState) +
+                                    " state words; this program needs " + std::to_string(ns));
+    std::string arch;
+    int dev = -1;
+    if (int rc = jit_target(arch_in, &arch, &dev)) return rc;
+    std::vector<char> code;
+    if (int rc = jit_code(src, arch, &code)) return rc;
+    JitPlanes* K = new JitPlanes;
+    K->n_state = ns;
+    if (dev >= 0) {
+        hipError_t e = hipModuleLoadData(&K->mod, code.data());
+        if (e == hipSuccess) e = hipModuleGetFunction(&K->fn, K->mod, "rx_sliced_planes");
+        if (e == hipSuccess) e = hipFuncGetAttribute(&K->scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, K->fn);
+        if (e != hipSuccess) {
+            if (K->mod) hipModuleUnload(K->mod);
+            delete K;
+            return fail(RX_EHIP, std::string("plane-form kernel: ") + hipGetErrorString(e));
+        }
+        K->dev = dev;
+    }
+    jit_planes_free(P);
+    P->jit_planes = K;
+    return RX_OK;
+}
+
+void jit_planes_free(Program* P) {
+    JitPlanes* K = static_cast<JitPlanes*>(P->jit_planes);
+    if (!K) return;
+    if (K->mod) hipModuleUnload(K->mod);
+    delete K;
+    P->jit_planes = nullptr;
+}
+
+bool jit_planes_ready(const Program* P, int* n_state, int* scratch) {
+    const JitPlanes* K = static_cast<const JitPlanes*>(P->jit_planes);
+    if (n_state) *n_state = K ? K->n_state : 0;
+    if (scratch) *scratch = K ? K->scratch : 0;
+    return K && K->fn;
+}
+
+int launch_sliced_planes(const Program* P, const uint32_t* planes, const int64_t* slab_tick, const int32_t* sorted,
+                         const int64_t* counts, int64_t max_slabs, uint8_t* out, void* stream) {
+    const JitPlanes* K = static_cast<const JitPlanes*>(P->jit_planes);
+    if (!K || !K->fn) return (int)hipErrorInvalidValue;
+    if (max_slabs <= 0) return 0;
+    const void* a0 = planes;
+    const void* a1 = slab_tick;
+    const void* a2 = sorted;
+    const void* a3 = counts;
+    void* a4 = out;
+    void* args[] = {&a0, &a1, &a2, &a3, &a4};
+    return (int)hipModuleLaunchKernel(K->fn, (unsigned)max_slabs, 1, 1, 64, 1, 1, 0, (hipStream_t)stream, args,
+                                      nullptr);
+}
+
+int jit_compile(Program* P, const char* arch_in) {
+    int ns = 0, nops = 0;
+    const std::string src = jit_full_source(*P, &ns, &nops);
+    if (ns > kJitMaxState)
+        return fail(RX_ETOOBIG, "the bit-sliced circuit keeps at most " + std::to_string(kJitMaxState) +
+                                    " state words in registers; this program needs " + std::to_string(ns));
+    std::string arch;
+    int dev = -1;
+    if (int rc = jit_target(arch_in, &arch, &dev)) return rc;
+    std::vector<char> code;
+    if (int rc = jit_code(src, arch, &code)) return rc;
     JitKernel* K = new JitKernel;
     K->arch = arch;
     K->n_state = ns;

@@ -15,6 +15,7 @@
 #include <cstdint>
 
 #include "rx_internal.h"
+#include "rx_planes.h"
 
 namespace rx {
 
@@ -268,7 +269,339 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(BucketArgs a) {
     }
 }
 
+// -- plane form: exact-length sort, slabs, bit planes ------------------------
+//
+// Strings shorter than kSortBins - 1 bytes are counting-sorted by length, so
+// a slab of 2048 consecutive sorted strings spans lengths close together;
+// longer strings (rare) are left to the table-form item kernel.  A slab runs
+// ceil(max length / 4) ticks; the planes of all slabs are gathered and
+// transposed once per call, then every program's circuit reads them.
+
+struct SortArgs {
+    const int64_t* offsets;
+    int64_t n;
+    int32_t* counts;   // [kSortBins]
+    int32_t* cursor;   // [kSortBins]
+    int32_t* start;    // [kSortBins + 1]
+    int64_t* info;     // [0] strings in slabs, [1] longer strings, [2] plane chunks (16 positions of a slab)
+    int32_t* sorted;   // [n]: slab strings by length, then the longer ones
+    int64_t* slab_tick;   // [max_slabs + 1]
+    int64_t* slab_chunk;  // [max_slabs + 1]
+    int64_t max_slabs;
+    int64_t tick_cap;     // ticks the plane buffer holds
+};
+
+__device__ __forceinline__ int sort_bin(int64_t len) { return len < kSortBins - 1 ? (int)len : kSortBins - 1; }
+
+__global__ void k_sort_clear(SortArgs a) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kSortBins; i += gridDim.x * blockDim.x) {
+        a.counts[i] = 0;
+        a.cursor[i] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sort_count(SortArgs a) {
+    __shared__ int32_t h[kSortBins];
+    for (int i = threadIdx.x; i < kSortBins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    int64_t r0, r1;
+    wg_range(a.n, r0, r1);
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) atomicAdd(&h[sort_bin(a.offsets[i + 1] - a.offsets[i])], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kSortBins; i += blockDim.x)
+        if (h[i]) atomicAdd(&a.counts[i], h[i]);
+}
+
+// One workgroup of 1024 threads: bin starts (exclusive scan), the split
+// between slab strings and longer ones.
+__global__ __launch_bounds__(1024) void k_sort_scan(SortArgs a) {
+    __shared__ int32_t part[1024];
+    constexpr int per = (kSortBins + 1023) / 1024;
+    const int b0 = threadIdx.x * per;
+    int32_t sum = 0;
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < kSortBins) sum += a.counts[b0 + k];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {   // inclusive scan of the parts
+        const int32_t v = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int32_t run = part[threadIdx.x] - sum;
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < kSortBins) {
+            a.start[b0 + k] = run;
+            run += a.counts[b0 + k];
+        }
+    if (threadIdx.x == 1023) {
+        a.start[kSortBins] = part[1023];
+        a.info[0] = part[1023] - a.counts[kSortBins - 1];
+        a.info[1] = a.counts[kSortBins - 1];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sort_scatter(SortArgs a) {
+    __shared__ int32_t h[kSortBins];
+    __shared__ int32_t g[kSortBins];
+    for (int i = threadIdx.x; i < kSortBins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    int64_t r0, r1;
+    wg_range(a.n, r0, r1);
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) atomicAdd(&h[sort_bin(a.offsets[i + 1] - a.offsets[i])], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kSortBins; i += blockDim.x) {
+        g[i] = h[i] ? atomicAdd(&a.cursor[i], h[i]) : 0;
+        h[i] = 0;
+    }
+    __syncthreads();
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        const int b = sort_bin(a.offsets[i + 1] - a.offsets[i]);
+        const int32_t pos = atomicAdd(&h[b], 1);
+        a.sorted[a.start[b] + g[b] + pos] = (int32_t)i;
+    }
+}
+
+// One workgroup of 1024 threads: ticks of every slab (its longest string is
+// its last), their prefix sums, and the 16-position chunks the plane kernel
+// works in.  If the total would pass the plane buffer's capacity (only when
+// the caller's byte bound is below the real total), every slab gets no ticks:
+// nothing is read or written past the buffer, and info[3] is set.
+__global__ __launch_bounds__(1024) void k_slab_scan(SortArgs a) {
+    __shared__ int64_t part[1024], cpart[1024];
+    const int64_t n_sliced = a.info[0];
+    const int64_t S = (n_sliced + kSlabStrings - 1) / kSlabStrings;
+    const int64_t per = (S + 1023) / 1024;
+    const int64_t s0 = (int64_t)threadIdx.x * per;
+    auto ticks_of = [&](int64_t s) -> int64_t {
+        const int64_t last = s * kSlabStrings + kSlabStrings - 1 < n_sliced ? s * kSlabStrings + kSlabStrings - 1
+                                                                              : n_sliced - 1;
+        const int32_t id = a.sorted[last];
+        return (a.offsets[id + 1] - a.offsets[id] + 3) / 4;
+    };
+    int64_t sum = 0, csum = 0;
+    for (int64_t k = 0; k < per; ++k)
+        if (s0 + k < S) {
+            const int64_t t = ticks_of(s0 + k);
+            sum += t;
+            csum += (t + 3) / 4;
+        }
+    part[threadIdx.x] = sum;
+    cpart[threadIdx.x] = csum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int64_t v = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+        const int64_t cv = threadIdx.x >= d ? cpart[threadIdx.x - d] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        cpart[threadIdx.x] += cv;
+        __syncthreads();
+    }
+    const bool over = part[1023] > a.tick_cap;
+    int64_t run = part[threadIdx.x] - sum, crun = cpart[threadIdx.x] - csum;
+    for (int64_t k = 0; k < per; ++k)
+        if (s0 + k < S) {
+            a.slab_tick[s0 + k] = over ? 0 : run;
+            a.slab_chunk[s0 + k] = over ? 0 : crun;
+            const int64_t t = ticks_of(s0 + k);
+            run += t;
+            crun += (t + 3) / 4;
+        }
+    if (threadIdx.x == 1023) {
+        a.slab_tick[S] = over ? 0 : part[1023];
+        a.slab_chunk[S] = over ? 0 : cpart[1023];
+        a.info[2] = over ? 0 : cpart[1023];
+        a.info[3] = over ? 1 : 0;
+    }
+}
+
+struct PlanesArgs {
+    const uint8_t* bytes;
+    const int64_t* offsets;
+    const int32_t* sorted;
+    const int64_t* info;
+    const int64_t* slab_tick;
+    const int64_t* slab_chunk;
+    uint32_t* planes;
+};
+
+// Gathers and transposes: one wavefront per (slab, 16 positions), persistent.
+// Lane l reads a 16-byte window of each of its 32 strings, then writes four
+// ticks of plane words (coalesced: 1 KiB per group of four words).
+__global__ __launch_bounds__(256) void k_planes(PlanesArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t n_sliced = a.info[0];
+    const int64_t S = (n_sliced + kSlabStrings - 1) / kSlabStrings;
+    const int64_t chunks = a.info[2];
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g < chunks; g += waves) {
+        // the slab holding chunk g: the last s with slab_chunk[s] <= g
+        int64_t lo = 0, hi = S - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (a.slab_chunk[mid] <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t s = lo;
+        const int64_t c = g - a.slab_chunk[s];
+        const int64_t t_base = a.slab_tick[s], T = a.slab_tick[s + 1] - t_base;
+        const int64_t first = a.sorted[s * kSlabStrings];
+        const int64_t minlen = a.offsets[first + 1] - a.offsets[first];
+        uint32_t win[32][4];
+        int64_t len[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            const int64_t k = s * kSlabStrings + j * 64 + lane;
+            int64_t lo_b = 0, ln = 0;
+            if (k < n_sliced) {
+                const int32_t id = a.sorted[k];
+                lo_b = a.offsets[id];
+                ln = a.offsets[id + 1] - lo_b;
+            }
+            len[j] = ln;
+            planes_window16(a.bytes + lo_b, ln, 16 * c, win[j]);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t t = 4 * c + k;
+            if (t >= T) break;
+            uint32_t w[kPlaneTickWords];
+            planes_tick(win, len, k, 4 * t, minlen, w);
+            uint4* dst = reinterpret_cast<uint4*>(a.planes) + (t_base + t) * (9 * 64) + lane;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) dst[q * 64] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+        }
+    }
+}
+
+// Work items for the strings too long for slabs: every program, 256 of them
+// per item, indices into `sorted` after the slab strings.
+struct OverArgs {
+    const int64_t* info;
+    WorkItem* items;
+    int32_t* n_items;
+    int32_t* head;
+    int32_t n_progs, block_lines;
+    int64_t out_stride;
+};
+
+__global__ void k_over_fill(OverArgs a) {
+    const int64_t n_sliced = a.info[0], n_over = a.info[1];
+    const int64_t tiles = (n_over + a.block_lines - 1) / a.block_lines;
+    const int64_t total = tiles * a.n_progs;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *a.n_items = (int32_t)total;
+        *a.head = 0;
+    }
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = k / tiles, t = k % tiles;
+        WorkItem w;
+        w.prog = (int32_t)p;
+        w.count = (int32_t)(n_over - t * a.block_lines < a.block_lines ? n_over - t * a.block_lines : a.block_lines);
+        w.line0 = n_sliced + t * a.block_lines;
+        w.out0 = p * a.out_stride;
+        a.items[k] = w;
+    }
+}
+
 }  // namespace
+
+int64_t plane_max_slabs(int64_t n) { return (n + kSlabStrings - 1) / kSlabStrings; }
+
+int64_t plane_tick_cap(int64_t n, int64_t max_bytes) {
+    // sorted by exact length, every slab but the last two is no longer than the
+    // shortest string of the next one: sum of slab lengths <= bytes / 2048 +
+    // 2 (kSortBins - 2); a slab's ticks are its length / 4 rounded up
+    return max_bytes / (4 * kSlabStrings) + (kSortBins - 2) / 2 + plane_max_slabs(n) + 2;
+}
+
+int64_t plane_workspace_bytes(int64_t n, int64_t max_bytes, int32_t n_progs, int32_t block_lines) {
+    auto al = [](int64_t x) { return (x + 255) & ~int64_t(255); };
+    if (block_lines <= 0) block_lines = 256;
+    const int64_t S = plane_max_slabs(n);
+    return al(4 * (3 * (int64_t)kSortBins + 1)) + al(8 * 8) + al(4 * n) + 2 * al(8 * (S + 1)) + al(8 * 4) +
+           al((int64_t)sizeof(WorkItem) * (int64_t)n_progs * (n / block_lines + 1)) +
+           al(plane_tick_cap(n, max_bytes) * kPlaneTickWords * 64 * 4);
+}
+
+int launch_planes_multi(const PlaneMultiArgs& m) {
+    const hipStream_t st = (hipStream_t)m.stream;
+    auto al = [](int64_t x) { return (x + 255) & ~int64_t(255); };
+    uint8_t* w = static_cast<uint8_t*>(m.work);
+    const int64_t S = plane_max_slabs(m.n);
+    SortArgs a;
+    a.offsets = m.offsets;
+    a.n = m.n;
+    a.counts = reinterpret_cast<int32_t*>(w);
+    a.cursor = a.counts + kSortBins;
+    a.start = a.cursor + kSortBins;
+    w += al(4 * (3 * (int64_t)kSortBins + 1));
+    a.info = reinterpret_cast<int64_t*>(w);
+    w += al(8 * 8);
+    a.sorted = reinterpret_cast<int32_t*>(w);
+    w += al(4 * m.n);
+    a.slab_tick = reinterpret_cast<int64_t*>(w);
+    w += al(8 * (S + 1));
+    a.slab_chunk = reinterpret_cast<int64_t*>(w);
+    w += al(8 * (S + 1));
+    int32_t* q = reinterpret_cast<int32_t*>(w);   // item count, queue head
+    w += al(8 * 4);
+    WorkItem* items = reinterpret_cast<WorkItem*>(w);
+    w += al((int64_t)sizeof(WorkItem) * (int64_t)m.n_progs * (m.n / m.block_lines + 1));
+    uint32_t* planes = reinterpret_cast<uint32_t*>(w);
+    a.max_slabs = S;
+    a.tick_cap = plane_tick_cap(m.n, m.max_bytes);
+    const int gs = (int)((m.n + 255) / 256 < 1024 ? (m.n + 255) / 256 : 1024);
+    hipLaunchKernelGGL(k_sort_clear, dim3((kSortBins + 255) / 256), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_sort_count, dim3(gs > 0 ? gs : 1), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(gs > 0 ? gs : 1), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_slab_scan, dim3(1), dim3(1024), 0, st, a);
+    PlanesArgs pa;
+    pa.bytes = m.bytes;
+    pa.offsets = m.offsets;
+    pa.sorted = a.sorted;
+    pa.info = a.info;
+    pa.slab_tick = a.slab_tick;
+    pa.slab_chunk = a.slab_chunk;
+    pa.planes = planes;
+    hipLaunchKernelGGL(k_planes, dim3(m.plane_grid), dim3(256), 0, st, pa);
+    if (hipError_t e = hipGetLastError()) return (int)e;
+    // every program's circuit over the slabs
+    for (int i = 0; i < m.n_progs; ++i)
+        if (int e = launch_sliced_planes(m.progs[i], planes, a.slab_tick, a.sorted, a.info, S, m.out + (int64_t)i * m.n,
+                                         m.stream))
+            return e;
+    // strings too long for a slab: table form, every program
+    OverArgs o;
+    o.info = a.info;
+    o.items = items;
+    o.n_items = q;
+    o.head = q + 1;
+    o.n_progs = m.n_progs;
+    o.block_lines = m.block_lines;
+    o.out_stride = m.n;
+    hipLaunchKernelGGL(k_over_fill, dim3(64), dim3(256), 0, st, o);
+    ItemKArgs k;
+    for (int i = 0; i < m.n_progs; ++i) k.progs[i] = m.descs[i];
+    k.n_progs = m.n_progs;
+    k.block_lines = m.block_lines;
+    k.bytes = m.bytes;
+    k.offsets = m.offsets;
+    k.ids = a.sorted;
+    k.items = items;
+    k.n_items = q;
+    k.head = q + 1;
+    k.out = m.out;
+    int max_lds_words = 0;
+    for (int i = 0; i < m.n_progs; ++i) {
+        const int words = (256 + m.descs[i].L) * m.descs[i].W;
+        if (words > max_lds_words) max_lds_words = words;
+    }
+    hipLaunchKernelGGL(k_items, dim3(m.item_grid), dim3(m.block_lines), 4 * (size_t)max_lds_words, st, k);
+    return (int)hipGetLastError();
+}
 
 int64_t multi_workspace_bytes(int64_t n, int32_t n_progs, int32_t n_buckets, int32_t block_lines) {
     auto al = [](int64_t x) { return (x + 255) & ~int64_t(255); };

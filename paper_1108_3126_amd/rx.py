@@ -48,16 +48,21 @@ class rx_node(ctypes.Structure):
 
 class rx_multi_config(ctypes.Structure):
     _fields_ = [("n_edges", ctypes.c_int32), ("edges", ctypes.c_int32 * 15), ("block", ctypes.c_int32),
-                ("grid", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("form", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_bytes", ctypes.c_int64)]
 
 
-def multi_config(edges=None, block=0, grid=0) -> "rx_multi_config":
+FORM_TABLE, FORM_PLANES = 0, 1
+
+
+def multi_config(edges=None, block=0, grid=0, form=FORM_TABLE, max_bytes=0) -> "rx_multi_config":
     c = rx_multi_config()
     if edges:
         c.n_edges = len(edges)
         for i, e in enumerate(edges):
             c.edges[i] = int(e)
     c.block, c.grid = int(block), int(grid)
+    c.form, c.max_bytes = int(form), int(max_bytes)
     return c
 
 
@@ -99,6 +104,9 @@ SIGNATURES = {
     "rx_program_jit_stats": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "rx_program_jit_staging": (ctypes.c_int, [_VP, ctypes.POINTER(_I32)]),
     "rx_program_jit_guard": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "rx_program_jit_planes": (ctypes.c_int, [_VP, ctypes.c_char_p]),
+    "rx_program_jit_planes_source": (ctypes.c_int, [_VP, ctypes.c_char_p, _SZ, ctypes.POINTER(_SZ)]),
+    "rx_program_planes_info": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "rx_isa_check_staging": (ctypes.c_int, [ctypes.c_char_p, _SZ, ctypes.c_char_p, ctypes.c_char_p,
                                             ctypes.POINTER(_I32)]),
     "rx_match_first": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _VP]),
@@ -263,6 +271,23 @@ class Program:
         """Generate and compile the bit-sliced circuit kernel (hiprtc)."""
         _check(lib().rx_program_jit(self._h, arch.encode() if arch else None))
         return self
+
+    def jit_planes(self, arch=None):
+        """Generate and compile the plane-form circuit (strings of any length, rx_match_multi RX_FORM_PLANES)."""
+        _check(lib().rx_program_jit_planes(self._h, arch.encode() if arch else None))
+        return self
+
+    def planes_info(self):
+        r, ns, sp = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().rx_program_planes_info(self._h, ctypes.byref(r), ctypes.byref(ns), ctypes.byref(sp)))
+        return {"ready": r.value, "state_words": ns.value, "spill_bytes": sp.value}
+
+    def jit_planes_source(self) -> str:
+        n = ctypes.c_size_t()
+        _check(lib().rx_program_jit_planes_source(self._h, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value + 1)
+        _check(lib().rx_program_jit_planes_source(self._h, buf, n.value + 1, ctypes.byref(n)))
+        return buf.value.decode()
 
     def jit_source(self) -> str:
         n = ctypes.c_size_t()
@@ -519,6 +544,9 @@ def match_multi(progs, data, offsets, out=None, config=None, work=None, stream=N
         if p._dev_buf is None:
             p.upload(device=offsets.device, stream=stream)
     cfg = config if config is not None else rx_multi_config()
+    if cfg.form == FORM_PLANES and cfg.max_bytes < data.numel():
+        # the plane workspace is sized by a bound on the total string bytes: the buffer's size
+        cfg = multi_config(list(cfg.edges)[:cfg.n_edges], cfg.block, cfg.grid, FORM_PLANES, data.numel())
     need = lib().rx_match_multi_workspace(n, P, ctypes.byref(cfg))
     if need < 0:
         _check(int(need))

@@ -70,3 +70,71 @@ def test_multi_edge_cases(dev):
     # zero strings
     z = rx.match_multi(ps, torch.zeros(1, dtype=torch.uint8, device=dev), torch.zeros(1, dtype=torch.int64, device=dev))
     assert z.shape == (3, 0)
+
+
+# -- plane form: the bit-sliced circuit over length-sorted slabs -----------------
+def _planes(rx, ps):
+    for p in ps:
+        p.jit_planes()
+        assert p.planes_info()["ready"] == 1
+    return rx.multi_config(form=rx.FORM_PLANES)
+
+
+def test_planes_match_oracle(dev, multi_case):
+    from paper_1108_3126_amd import rx
+
+    progs, s, want = multi_case
+    ps = [rx.compile(p.ast, p.root, p.classes, p.search).upload(dev) for p in progs]
+    cfg = _planes(rx, ps)
+    d, o = torch.from_numpy(s.data).to(dev), torch.from_numpy(s.offsets).to(dev)
+    got = rx.match_multi(ps, d, o, config=cfg).cpu().numpy()
+    assert np.array_equal(got, want)
+
+
+def test_planes_edge_cases(dev):
+    """Empty strings, one-byte strings, lengths around the slab and sort limits (8190 sorts, 8191 and
+    longer run in table form), a partial last slab, unaligned offsets, anchored and searched."""
+    from paper_1108_3126_amd import rx
+
+    progs = W.multi_programs(seed=41, count=3, lo=8, hi=60) + [W.small_program(5)]
+    rng = np.random.default_rng(9)
+    strs = [b"", b"a", b"ab", b"e" * 8190, b"e" * 8191, b"the quick brown" * 700, b""]
+    strs += [bytes(rng.integers(32, 127, size=int(rng.integers(0, 90)), dtype=np.uint8)) for _ in range(4200)]
+    strs += [b"ab" * int(k) for k in rng.integers(0, 40, size=300)]
+    s = W.pack(strs)
+    want = _oracle_all(progs, s)
+    ps = [rx.compile(p.ast, p.root, p.classes, p.search).upload(dev) for p in progs]
+    cfg = _planes(rx, ps)
+    # the strings one byte into the buffer: every offset unaligned
+    buf = np.concatenate([np.zeros(1, np.uint8), s.data])
+    d = torch.from_numpy(buf).to(dev)
+    o = torch.from_numpy(s.offsets + 1).to(dev)
+    got = rx.match_multi(ps, d, o, config=cfg).cpu().numpy()
+    bad = np.nonzero(got != want)
+    assert bad[0].size == 0, list(zip(bad[0][:5], bad[1][:5]))
+    # the table form agrees
+    assert np.array_equal(rx.match_multi(ps, d, o).cpu().numpy(), want)
+    # one string; no strings
+    one = W.pack([b"xyz"])
+    got1 = rx.match_multi(ps, torch.from_numpy(one.data).to(dev), torch.from_numpy(one.offsets).to(dev),
+                          config=cfg).cpu().numpy()
+    assert np.array_equal(got1, _oracle_all(progs, one))
+    z = rx.match_multi(ps, torch.zeros(1, dtype=torch.uint8, device=dev), torch.zeros(1, dtype=torch.int64, device=dev),
+                       config=cfg)
+    assert z.shape == (4, 0)
+
+
+def test_planes_repeat_calls_share_workspace(dev, multi_case):
+    """The same workspace for two calls in a row, the second smaller: every counter is cleared by the
+    call's own kernels."""
+    from paper_1108_3126_amd import rx
+
+    progs, s, want = multi_case
+    ps = [rx.compile(p.ast, p.root, p.classes, p.search).upload(dev) for p in progs[:3]]
+    cfg = _planes(rx, ps)
+    d, o = torch.from_numpy(s.data).to(dev), torch.from_numpy(s.offsets).to(dev)
+    work = torch.empty(1 << 26, dtype=torch.uint8, device=dev)
+    a = rx.match_multi(ps, d, o, config=cfg, work=work).cpu().numpy()
+    o2 = torch.from_numpy(s.offsets[:1001].copy()).to(dev)
+    b = rx.match_multi(ps, d, o2, config=cfg, work=work).cpu().numpy()
+    assert np.array_equal(a, want[:3]) and np.array_equal(b, want[:3, :1000])

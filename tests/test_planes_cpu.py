@@ -1,0 +1,233 @@
+"""The plane form of the bit-sliced circuit on the CPU: the gather-and-transpose
+code (rx_planes.h) compiled with g++ against a bit-by-bit construction of the
+planes, and the generated plane-form circuit (the same source text hiprtc
+compiles) driven by those planes over strings of uneven length, against the
+oracle.  No GPU: the device build maps the three primitives to single
+instructions; here they are plain C."""
+import ctypes
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1108_3126_amd import rx
+from paper_1108_3126_amd import workloads as W
+
+CSRC = os.path.join(os.path.dirname(rx.__file__), "csrc")
+
+HOST_PRIMS = r"""
+#include <cstdint>
+#include <cstddef>
+static inline uint32_t pl_perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+    const uint64_t v = ((uint64_t)hi << 32) | lo;
+    uint32_t r = 0;
+    for (int i = 0; i < 4; ++i) r |= (uint32_t)((v >> (8 * ((sel >> (8 * i)) & 7))) & 0xff) << (8 * i);
+    return r;
+}
+static inline uint32_t pl_align(uint32_t hi, uint32_t lo, uint32_t r) {
+    return (uint32_t)((((uint64_t)hi << 32) | lo) >> (8 * (r & 3)));
+}
+#define RX_PL_DEV static inline
+#define RX_PL_PERM(hi, lo, sel) pl_perm((hi), (lo), (sel))
+#define RX_PL_SEL(a, b, m) ((((uint32_t)(a)) & (m)) | (((uint32_t)(b)) & ~(m)))
+#define RX_PL_ALIGN(hi, lo, r) pl_align((hi), (lo), (r))
+"""
+
+# One slab (up to 2048 strings given by pointers into one buffer): all ticks of
+# every lane, laid out as on the device (((t * 9 + q) * 64 + lane) * 4 + r).
+SLAB_DRIVER = r"""
+#include "rx_planes.h"
+extern "C" void slab_planes(const uint8_t* bytes, const int64_t* lo, const int64_t* len, int64_t count,
+                            int64_t ticks, uint32_t* out) {
+    int64_t minlen = count ? len[0] : 0;
+    for (int64_t k = 0; k < count; ++k) if (len[k] < minlen) minlen = len[k];
+    if (count < 2048) minlen = 0;   // missing strings have length 0
+    for (int lane = 0; lane < 64; ++lane) {
+        for (int64_t c = 0; 4 * c < ticks; ++c) {
+            uint32_t win[32][4];
+            int64_t L[32];
+            for (int j = 0; j < 32; ++j) {
+                const int64_t k = j * 64 + lane;
+                const int64_t o = k < count ? lo[k] : 0, n = k < count ? len[k] : 0;
+                L[j] = n;
+                rx::planes_window16(bytes + o, n, 16 * c, win[j]);
+            }
+            for (int kk = 0; kk < 4 && 4 * c + kk < ticks; ++kk) {
+                uint32_t w[36];
+                const int64_t t = 4 * c + kk;
+                rx::planes_tick(win, L, kk, 4 * t, minlen, w);
+                for (int q = 0; q < 9; ++q)
+                    for (int r = 0; r < 4; ++r) out[((t * 9 + q) * 64 + lane) * 4 + r] = w[4 * q + r];
+            }
+        }
+    }
+}
+"""
+
+
+def _build(code, name):
+    d = tempfile.mkdtemp(prefix="rxpl")
+    cpp, so = os.path.join(d, name + ".cpp"), os.path.join(d, name + ".so")
+    open(cpp, "w").write(code)
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-w", "-I", CSRC, "-o", so, cpp])
+    return ctypes.CDLL(so)
+
+
+@pytest.fixture(scope="module")
+def slab_lib():
+    lib = _build(HOST_PRIMS + SLAB_DRIVER, "slab")
+    lib.slab_planes.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]
+    return lib
+
+
+def slab_planes(lib, buf, lo, ln, ticks):
+    lo = np.ascontiguousarray(lo, np.int64)
+    ln = np.ascontiguousarray(ln, np.int64)
+    out = np.zeros(ticks * 9 * 64 * 4, np.uint32)
+    lib.slab_planes(buf.ctypes.data, lo.ctypes.data, ln.ctypes.data, len(lo), ticks, out.ctypes.data)
+    return out.reshape(ticks, 9, 64, 4)
+
+
+def naive_planes(buf, lo, ln, ticks):
+    """Bit by bit: plane b of position p, lane l, bit j = bit b of string (64 j + l)'s byte p."""
+    out = np.zeros((ticks, 9, 64, 4), np.uint64)
+    for k in range(len(lo)):
+        j, lane = divmod(k, 64)
+        for p in range(min(int(ln[k]), 4 * ticks)):
+            byte = int(buf[lo[k] + p])
+            t, i = divmod(p, 4)
+            for b in range(8):
+                if (byte >> b) & 1:
+                    w = 8 * i + b
+                    out[t, w // 4, lane, w % 4] |= 1 << j
+            out[t, 8, lane, i] |= 1 << j   # the string has byte p
+    return out.astype(np.uint32)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_planes_match_bit_by_bit_construction(slab_lib, seed):
+    rng = np.random.default_rng(seed)
+    count = [2048, 2048, 700][seed]
+    ln = np.sort(rng.integers(0, 70, size=count)) if seed != 1 else rng.integers(0, 70, size=count)
+    # every string at an odd, unaligned place in one buffer, with foreign bytes in between
+    gaps = rng.integers(0, 19, size=count)
+    lo = np.zeros(count, np.int64)
+    pos = 3
+    for k in range(count):
+        pos += int(gaps[k])
+        lo[k] = pos
+        pos += int(ln[k])
+    buf = rng.integers(0, 256, size=pos + 64, dtype=np.uint8)
+    ticks = (int(ln.max()) + 3) // 4
+    got = slab_planes(slab_lib, buf, lo, ln, ticks)
+    want = naive_planes(buf, lo, ln, ticks)
+    # bytes past a string's end are unspecified in the planes; the valid words must be exact
+    valid = want[:, 8]
+    assert np.array_equal(got[:, 8], valid)
+    for t in range(ticks):
+        for w in range(32):
+            i = w // 8
+            vmask = valid[t, :, i]
+            assert np.array_equal(got[t, w // 4, :, w % 4] & vmask, want[t, w // 4, :, w % 4]), (t, w)
+
+
+CIRCUIT_DRIVER = r"""
+#include "rx_planes.h"
+// Every slab of the given strings (in order, 2048 per slab) through the
+// plane-form circuit: tick by tick, as the device kernel runs it.
+extern "C" void run_planes(const uint8_t* bytes, const int64_t* lo, const int64_t* len, int64_t n,
+                           unsigned char* out) {
+    for (int64_t s0 = 0; s0 < n; s0 += 2048) {
+        const int64_t count = n - s0 < 2048 ? n - s0 : 2048;
+        int64_t mx = 0;
+        for (int64_t k = 0; k < count; ++k) if (len[s0 + k] > mx) mx = len[s0 + k];
+        const int64_t ticks = (mx + 3) / 4;
+        for (int lane = 0; lane < 64; ++lane) {
+            u32 st[RX_NS];
+            u32 acc;
+            rx_init(st, acc);
+            u32 accf = acc;
+            for (int64_t c = 0; 4 * c < ticks; ++c) {
+                uint32_t win[32][4];
+                int64_t L[32];
+                for (int j = 0; j < 32; ++j) {
+                    const int64_t k = j * 64 + lane;
+                    const int64_t o = k < count ? lo[s0 + k] : 0, m = k < count ? len[s0 + k] : 0;
+                    L[j] = m;
+                    rx::planes_window16(bytes + o, m, 16 * c, win[j]);
+                }
+                for (int kk = 0; kk < 4 && 4 * c + kk < ticks; ++kk) {
+                    u32 w[36];
+                    rx::planes_tick(win, L, kk, 4 * (4 * c + kk), 0, w);
+                    rx_planes_tick(st, acc, accf, w);
+                }
+            }
+            for (int j = 0; j < 32; ++j) {
+                const int64_t k = j * 64 + lane;
+                if (k < count) out[s0 + k] = (unsigned char)((accf >> j) & 1u);
+            }
+        }
+    }
+}
+"""
+
+PERM_CPU = r"""
+static inline unsigned rx_perm_cpu(unsigned hi, unsigned lo, unsigned sel) {
+    const unsigned long long v = ((unsigned long long)hi << 32) | lo;
+    unsigned r = 0;
+    for (int i = 0; i < 4; ++i) r |= (unsigned)((v >> (8 * ((sel >> (8 * i)) & 7))) & 0xff) << (8 * i);
+    return r;
+}
+"""
+
+
+def planes_circuit(p):
+    src = p.jit_planes_source()
+    host_part = src.split("// ---- device kernel ----")[0]
+    code = ("#define __device__\n#define __forceinline__ inline\n" + PERM_CPU + host_part + HOST_PRIMS +
+            CIRCUIT_DRIVER)
+    lib = _build(code, "circ")
+    lib.run_planes.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_void_p]
+
+    def run(s):
+        lo = np.ascontiguousarray(s.offsets[:-1], np.int64)
+        ln = np.ascontiguousarray(np.diff(s.offsets), np.int64)
+        data = s.data if s.data.size else np.zeros(16, np.uint8)
+        out = np.zeros(max(s.n, 1), np.uint8)
+        lib.run_planes(data.ctypes.data, lo.ctypes.data, ln.ctypes.data, s.n, out.ctypes.data)
+        return out[:s.n]
+
+    return run
+
+
+def test_plane_circuit_uneven_lengths_against_oracle():
+    prog = W.single_program(1)
+    p = rx.compile(prog.ast, prog.root, prog.classes, True)
+    rng = np.random.default_rng(4)
+    member, _ = W.single_strings(prog, seed=44, n=64, length=256, plant_frac=1.0)
+    strs = []
+    for k in range(3000):
+        n = int(rng.integers(0, 300))
+        w = bytes(rng.integers(97, 123, size=n, dtype=np.uint8))
+        if k % 5 == 0 and n > 0:   # a member of the language inside
+            m = member.get(k % 64)
+            at = int(rng.integers(0, n + 1))
+            w = (w[:at] + m + w[at:])
+        strs.append(w)
+    s = W.pack(strs)
+    got = planes_circuit(p)(s)
+    want = oracle.match(prog.ast, prog.root, prog.classes, True, s.data, s.offsets, threads=4)
+    assert got.sum() > 300 and np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_plane_circuit_small_anchored_programs(seed):
+    prog = W.small_program(seed)
+    p = rx.compile(prog.ast, prog.root, prog.classes, False)
+    s = W.small_strings(seed, n=2500)
+    got = planes_circuit(p)(s)
+    want = oracle.match(prog.ast, prog.root, prog.classes, False, s.data, s.offsets, threads=4)
+    assert np.array_equal(got, want)
