@@ -312,8 +312,7 @@ def run_multi(args, torch, dev):
     ms_table, got_table = timed(cfg)
     # plane form: each program's bit-sliced circuit over length-sorted slabs
     j0 = time.time()
-    for p in ps:
-        p.jit_planes()
+    rx.prepare_multi(ps)
     jit_s = time.time() - j0
     pcfg = rx.multi_config(form=rx.FORM_PLANES, max_bytes=int(lines.offsets[-1]))
     ms_planes, got = timed(pcfg)

@@ -396,22 +396,23 @@ int rx_program_jit_staging(const rx_program* prog, int32_t staged[7]);
  * shows what runs instead).  Errors: RX_EINVAL (NULL arguments). */
 int rx_program_jit_guard(const rx_program* prog, int32_t* ran, int32_t violations[8], int32_t* dropped);
 
-/* Generates and compiles the plane-form circuit of the program (its own small
- * module: the per-node processes of §7 as boolean signals over 32 strings per
- * word, fed precomputed bit planes), for rx_match_multi with RX_FORM_PLANES.
- * arch as for rx_program_jit.  Without a device the source is only compiled.
- * Programs keep their leaf states in registers where they fit; the device
- * compiler spills the rest.  Errors: RX_EJIT, RX_ETOOBIG (more than 1024
- * state words), RX_EHIP. */
-int rx_program_jit_planes(rx_program* prog, const char* arch);
+/* Generates and compiles the plane-form circuits of a list of programs, for
+ * rx_match_multi with RX_FORM_PLANES on that list (same programs, same
+ * order): one module holding every program's circuit (the per-node processes
+ * of §7 as boolean signals over 32 strings per word, fed precomputed bit
+ * planes), loaded on the current device and kept until the process ends.
+ * Repeated calls for a list already loaded return at once.  arch as for
+ * rx_program_jit (without a device the source is only compiled).  Programs
+ * keep their leaf states in registers where they fit; the device compiler
+ * spills the rest (*spill_bytes, may be NULL: private bytes per lane, 0 when
+ * everything fits).  Errors: RX_EINVAL, RX_EJIT, RX_ETOOBIG (a program above
+ * 1024 state words or more than 64 programs), RX_EHIP. */
+int rx_match_multi_prepare(const rx_program* const* progs, int32_t n_progs, const char* arch,
+                           int32_t* spill_bytes);
 
-/* The plane-form circuit's generated source, as rx_program_jit_source. */
+/* The plane-form source generated for the one-program list {prog}, as
+ * rx_program_jit_source. */
 int rx_program_jit_planes_source(const rx_program* prog, char* buf, size_t cap, size_t* len);
-
-/* ready = 1 when the plane-form circuit is loaded; state_words as in
- * rx_program_jit_stats; spill_bytes = per-lane private memory the device
- * compiler gave the kernel (register spills; 0 when everything fits). */
-int rx_program_planes_info(const rx_program* prog, int32_t* ready, int32_t* state_words, int32_t* spill_bytes);
 
 /* The same check on any code object (an AMDGPU ELF of len bytes, owned by the
  * caller) for the function `kernel` compiled for `arch` (e.g. "gfx950"):
@@ -462,9 +463,10 @@ int64_t rx_match_multi_workspace(int64_t n, int32_t n_progs, const rx_multi_conf
  * consecutive sorted strings, and every slab's bytes are gathered and
  * transposed once into bit planes (32 strings per word, plus one word per
  * position marking the strings that still have bytes).  Each program's
- * plane-form circuit (rx_program_jit_planes) then runs over all slabs, one
- * wavefront per slab, and keeps each string's accept bit as of its last byte.
- * Every program must have that circuit loaded on the current device;
+ * plane-form circuit then runs over all slabs -- one launch, one wavefront per
+ * (program, slab), longest slabs first -- and keeps each string's accept bit
+ * as of its last byte.  The list must have been prepared on the current
+ * device (rx_match_multi_prepare);
  * cfg->max_bytes must be at least the total length of the strings (with a
  * smaller bound the slabs are skipped and their results are unspecified; no
  * memory outside the workspace is touched).

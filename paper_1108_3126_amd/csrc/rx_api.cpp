@@ -91,10 +91,7 @@ int rx_compile(const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx_cla
 void rx_program_free(rx_program* prog) {
     try {
         Program* P = reinterpret_cast<Program*>(prog);
-        if (P) {
-            jit_free(P);
-            jit_planes_free(P);
-        }
+        if (P) jit_free(P);
         delete P;
     } catch (...) {
     }
@@ -580,8 +577,6 @@ int match_multi_planes(const rx_program* const* progs, int32_t n_progs, const ui
         if (!P) return fail(RX_EINVAL, "program " + std::to_string(i) + " is NULL");
         if (!P->dev) return fail(RX_ENOTUPLOADED, "program " + std::to_string(i) + " has not been uploaded");
         if (P->W > kLaneMaxWords) return fail(RX_ETOOBIG, "program " + std::to_string(i) + " holds more than 16 words");
-        if (!jit_planes_ready(P, nullptr, nullptr))
-            return fail(RX_EINVAL, "program " + std::to_string(i) + " has no plane-form circuit (rx_program_jit_planes)");
         const uint8_t* base = static_cast<const uint8_t*>(P->dev);
         m.progs[i] = P;
         m.descs[i].first = reinterpret_cast<const uint32_t*>(base + P->layout.first);
@@ -592,6 +587,8 @@ int match_multi_planes(const rx_program* const* progs, int32_t n_progs, const ui
         m.descs[i].suffix_any = P->suffix_any ? 1 : 0;
         m.descs[i].pad = 0;
     }
+    if (!jit_planes_prepared(m.progs, n_progs))
+        return fail(RX_EINVAL, "this program list has no plane-form module on the device (rx_match_multi_prepare)");
     m.n_progs = n_progs;
     m.block_lines = shape.block_lines;
     m.item_grid = shape.grid;
@@ -744,24 +741,23 @@ int rx_program_jit_staging(const rx_program* prog, int32_t staged[7]) {
     return RX_OK;
 }
 
-int rx_program_jit_planes(rx_program* prog, const char* arch) {
-    TraceRange trace_range_("rx_program_jit_planes");
+int rx_match_multi_prepare(const rx_program* const* progs, int32_t n_progs, const char* arch,
+                           int32_t* spill_bytes) {
+    TraceRange trace_range_("rx_match_multi_prepare");
     RX_GUARD_BEGIN
-    if (!prog) return fail(RX_EINVAL, "program is NULL");
-    int rc = jit_compile_planes(reinterpret_cast<Program*>(prog), arch);
+    if (n_progs <= 0 || !progs) return fail(RX_EINVAL, "no programs");
+    if (n_progs > kMaxItemProgs) return fail(RX_ETOOBIG, "at most 64 programs per call");
+    std::vector<const Program*> ps(n_progs);
+    for (int i = 0; i < n_progs; ++i) {
+        ps[i] = reinterpret_cast<const Program*>(progs[i]);
+        if (!ps[i]) return fail(RX_EINVAL, "program " + std::to_string(i) + " is NULL");
+    }
+    int sp = 0;
+    int rc = jit_prepare_planes(ps.data(), n_progs, arch, &sp);
+    if (spill_bytes) *spill_bytes = sp;
     if (rc == RX_OK) clear_error();
     return rc;
     RX_GUARD_END
-}
-
-int rx_program_planes_info(const rx_program* prog, int32_t* ready, int32_t* state_words, int32_t* spill_bytes) {
-    if (!prog) return fail(RX_EINVAL, "program is NULL");
-    int ns = 0, sc = 0;
-    const bool r = jit_planes_ready(reinterpret_cast<const Program*>(prog), &ns, &sc);
-    if (ready) *ready = r ? 1 : 0;
-    if (state_words) *state_words = ns;
-    if (spill_bytes) *spill_bytes = sc;
-    return RX_OK;
 }
 
 int rx_program_jit_guard(const rx_program* prog, int32_t* ran, int32_t violations[8], int32_t* dropped) {

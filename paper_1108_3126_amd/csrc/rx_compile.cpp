@@ -2,6 +2,7 @@
 // tables.  Follows Section 4 (heap, Def. 4.1; tree shape, Def. 4.3; cont,
 // Def. 4.4), the two passes of Section 8 (pack the nodes, then wire cont) and
 // Def. 5.1 (evolution) of Rathnayake & Thielecke, SOS 2011.
+#include <atomic>
 #include <algorithm>
 #include <cstring>
 #include <new>
@@ -82,6 +83,8 @@ int compile(const rx_ast_node* ast, int32_t n_ast, int32_t root, const rx_class*
 
     Program* P = new (std::nothrow) Program;
     if (!P) return fail(RX_ENOMEM, "out of host memory");
+    static std::atomic<uint64_t> next_uid{1};
+    P->uid = next_uid++;
     P->flags = flags;
     for (int32_t i = 0; i < n_classes; ++i) {
         std::array<uint64_t, 4> c;

@@ -49,8 +49,8 @@ struct Program {
     int dev_id = -1;
     // run-time generated kernel for the bit-sliced circuit (may be null)
     void* jit = nullptr;
-    // run-time generated plane-form circuit for strings of any length (may be null)
-    void* jit_planes = nullptr;
+    // identity for module caches: unique per compiled program in this process
+    uint64_t uid = 0;
 };
 
 // batched matching (rx_multi.hip)
@@ -198,14 +198,16 @@ void jit_free(Program* P);
 bool jit_ready(const Program* P, int* n_state, int* n_ops);
 // staged[u] for staging modes u = 0..5 (see rx_program_jit_staging).
 void jit_staging(const Program* P, int32_t staged[7]);
-// Plane-form circuit (rx_jit.cpp): its own small module per program.
-std::string jit_planes_source(const Program& P, int* n_state);
-int jit_compile_planes(Program* P, const char* arch);
-void jit_planes_free(Program* P);
-bool jit_planes_ready(const Program* P, int* n_state, int* scratch);
-// One wavefront per slab (grid max_slabs; slabs beyond counts[0] exit at once).
-int launch_sliced_planes(const Program* P, const uint32_t* planes, const int64_t* slab_tick, const int32_t* sorted,
-                         const int64_t* counts, int64_t max_slabs, uint8_t* out, void* stream);
+// Plane-form circuits (rx_jit.cpp): one module per list of programs.
+std::string jit_multi_planes_source(const Program* const* progs, int n, int* max_state);
+std::string jit_planes_source(const Program& P, int* n_state);   // the list of one program
+// Compiles and loads (once per device and list) the module of `progs`.
+int jit_prepare_planes(const Program* const* progs, int n, const char* arch, int* spill_bytes);
+bool jit_planes_prepared(const Program* const* progs, int n);
+// One wavefront per (program, slab); returns -1 when the list was not prepared.
+int launch_planes_circuits(const Program* const* progs, int n, const uint32_t* planes, const int64_t* slab_tick,
+                           const int32_t* sorted, const int64_t* info, int64_t max_slabs, uint8_t* out,
+                           int64_t n_strings, void* stream);
 // Static check of a register-staged kernel in a code object (rx_isa_guard.cpp):
 // *violations = instructions not written by the kernel itself that name an
 // accumulation register.  Returns 0 when the check ran, < 0 when it could not.

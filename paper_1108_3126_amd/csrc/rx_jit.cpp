@@ -848,7 +848,7 @@ extern "C" __global__ __launch_bounds__(64, 1) void rx_sliced_fixed_pf(const uns
 }
 )RX";
 
-// Plane form: the circuit driven by bit planes that a separate kernel has
+// Plane form: circuits driven by bit planes that a separate kernel has
 // already gathered and transposed (rx_multi.hip), for strings of any length.
 // A slab is 2048 strings (lane l holds strings 64 j + l in bit j); tick t of a
 // slab is positions 4t .. 4t+3 as 36 words per lane: w[8i + b] = bit plane b
@@ -857,33 +857,40 @@ extern "C" __global__ __launch_bounds__(64, 1) void rx_sliced_fixed_pf(const uns
 // u32 index ((t * 9 + q) * 64 + l) * 4.  After each step a string's accept
 // bit is taken only while the string still has bytes, so it holds the value
 // after the string's last byte (the start value for the empty string).
-const char* kPlanesSource = R"RX(
-__device__ __forceinline__ void rx_planes_tick(u32 (&s)[RX_NS], u32& acc, u32& accf, const u32 (&w)[36]) {
+//
+// One module holds the circuits of every program of a call (one struct per
+// program), so a single launch runs every (program, slab) pair: the longest
+// slabs of all programs start first, and the programs of one slab run side by
+// side on one XCD (workgroups go to the XCDs in turn, blockIdx mod 8), where
+// they share that slab's planes in the XCD's L2.
+const char* kPlanesTickSource = R"RX(
+template <class PR>
+__device__ __forceinline__ void rx_planes_tick(u32 (&s)[PR::NS], u32& acc, u32& accf, const u32 (&w)[36]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        rx_step(s, acc, w[8 * i], w[8 * i + 1], w[8 * i + 2], w[8 * i + 3], w[8 * i + 4], w[8 * i + 5],
-                w[8 * i + 6], w[8 * i + 7]);
+        PR::step(s, acc, w[8 * i], w[8 * i + 1], w[8 * i + 2], w[8 * i + 3], w[8 * i + 4], w[8 * i + 5],
+                 w[8 * i + 6], w[8 * i + 7]);
         const u32 v = w[32 + i];
         accf = (acc & v) | (accf & ~v);
     }
 }
+)RX";
+
+const char* kPlanesKernelSource = R"RX(
 // ---- device kernel ----
 typedef unsigned int rx_pv4 __attribute__((ext_vector_type(4)));
-// One wavefront per slab, longest slabs first.  slab_tick[s] .. slab_tick[s+1]
-// are the slab's ticks in `planes`; sorted[s * 2048 + k] is the string the
-// slab's k-th entry stands for; counts[0] is the number of strings in slabs.
-extern "C" __global__ __launch_bounds__(64) void rx_sliced_planes(const u32* __restrict__ planes,
-        const long long* __restrict__ slab_tick, const int* __restrict__ sorted, const long long* __restrict__ counts,
-        unsigned char* __restrict__ out) {
-    const long long n_sliced = counts[0];
-    const long long s = (n_sliced + 2047) / 2048 - 1 - (long long)blockIdx.x;
-    if (s < 0) return;
+// Slab s (ticks slab_tick[s] .. slab_tick[s+1] of `planes`) for program PR;
+// sorted[s * 2048 + k] is the string the slab's k-th entry stands for.
+template <class PR>
+__device__ __forceinline__ void rx_run_slab(const u32* __restrict__ planes, const long long* __restrict__ slab_tick,
+                                            const int* __restrict__ sorted, long long n_sliced, long long s,
+                                            unsigned char* __restrict__ out) {
     const int lane = threadIdx.x;
     const long long t0 = slab_tick[s], T = slab_tick[s + 1] - t0;
     const rx_pv4* p = reinterpret_cast<const rx_pv4*>(planes) + t0 * (9 * 64) + lane;
-    u32 st[RX_NS];
+    u32 st[PR::NS];
     u32 acc;
-    rx_init(st, acc);
+    PR::init(st, acc);
     u32 accf = acc;
     rx_pv4 cur[9];
 #pragma unroll
@@ -902,7 +909,7 @@ extern "C" __global__ __launch_bounds__(64) void rx_sliced_planes(const u32* __r
             w[4 * q + 2] = cur[q].z;
             w[4 * q + 3] = cur[q].w;
         }
-        rx_planes_tick(st, acc, accf, w);
+        rx_planes_tick<PR>(st, acc, accf, w);
 #pragma unroll
         for (int q = 0; q < 9; ++q) cur[q] = nxt[q];
     }
@@ -912,15 +919,76 @@ extern "C" __global__ __launch_bounds__(64) void rx_sliced_planes(const u32* __r
         if (k < n_sliced) out[sorted[k]] = (unsigned char)((accf >> j) & 1u);
     }
 }
+
+// One wavefront per (program, slab).  Workgroup b runs on XCD b mod 8; its
+// slab rank (0 = longest) is 8 * ((b / 8) / n_progs) + b mod 8 and its
+// program (b / 8) mod n_progs.  info[0] = strings in slabs; results of
+// program p go to out[p * n + string].
+extern "C" __global__ __launch_bounds__(64) void rx_planes_multi(const u32* __restrict__ planes,
+        const long long* __restrict__ slab_tick, const int* __restrict__ sorted, const long long* __restrict__ info,
+        unsigned char* __restrict__ out, long long n) {
+    const long long b = blockIdx.x;
+    const long long k = b >> 3;
+    const int p = (int)(k % RX_NPROGS);
+    const long long r = (k / RX_NPROGS) * 8 + (b & 7);
+    const long long n_sliced = info[0];
+    const long long S = (n_sliced + 2047) / 2048;
+    if (r >= S) return;
+    rx_dispatch(p, planes, slab_tick, sorted, n_sliced, S - 1 - r, out + p * n);
+}
 )RX";
 
-struct JitPlanes {
+// The plane-form source for a list of programs: program k's circuit as
+// struct RxProgk (its step and start state in namespace rxqk), the tick
+// template, a dispatch over the programs and the kernel.
+std::string jit_multi_planes_source(const Program* const* progs, int n, int* max_state) {
+    std::ostringstream s;
+    s << "typedef unsigned int u32;\n#define RX_NPROGS " << n << "\n";
+    int mx = 0;
+    for (int k = 0; k < n; ++k) {
+        int ns = 0;
+        std::string step = jit_step_source(*progs[k], &ns, nullptr);
+        if (ns < 1) ns = 1;
+        mx = std::max(mx, ns);
+        // the step source opens with its own #define of RX_NS
+        const size_t eol = step.find('\n');
+        s << "#define RX_NS " << ns << "\nnamespace rxq" << k << " {\n" << step.substr(eol + 1) << "}\n#undef RX_NS\n";
+        s << "struct RxProg" << k << " {\n    static constexpr int NS = " << ns << ";\n"
+          << "    __device__ static __forceinline__ void init(u32 (&s)[NS], u32& acc) { rxq" << k << "::rx_init(s, acc); }\n"
+          << "    __device__ static __forceinline__ void step(u32 (&s)[NS], u32& acc, u32 b0, u32 b1, u32 b2, u32 b3, "
+             "u32 b4, u32 b5, u32 b6, u32 b7) {\n        rxq" << k << "::rx_step(s, acc, b0, b1, b2, b3, b4, b5, b6, b7);\n    }\n};\n";
+    }
+    s << kPlanesTickSource;
+    // the kernel part starts with the device-only marker; the dispatch sits just after it
+    std::string kern = kPlanesKernelSource;
+    const std::string marker = "// ---- device kernel ----\n";
+    const size_t at = kern.find(marker) + marker.size();
+    std::ostringstream disp;
+    disp << kern.substr(0, kern.find("extern \"C\""));
+    disp << "__device__ __forceinline__ void rx_dispatch(int p, const u32* __restrict__ planes, const long long* "
+            "__restrict__ slab_tick, const int* __restrict__ sorted, long long n_sliced, long long s, unsigned char* "
+            "__restrict__ out) {\n    switch (p) {\n";
+    for (int k = 0; k < n; ++k)
+        disp << "    case " << k << ": rx_run_slab<RxProg" << k << ">(planes, slab_tick, sorted, n_sliced, s, out); break;\n";
+    disp << "    default: break;\n    }\n}\n";
+    disp << kern.substr(kern.find("extern \"C\""));
+    (void)at;
+    s << disp.str();
+    if (max_state) *max_state = mx;
+    return s.str();
+}
+
+// Loaded plane-form modules by (device, source): one per distinct program
+// list, kept until the process ends (a module may be running on a stream).
+struct PlaneModule {
     hipModule_t mod = nullptr;
     hipFunction_t fn = nullptr;
-    int dev = -1;
-    int n_state = 0;
-    int scratch = 0;   // private bytes per lane (register spills the compiler chose)
+    int scratch = 0;
 };
+namespace {
+std::mutex g_plane_mu;
+std::unordered_map<std::string, PlaneModule*> g_plane_mods;
+}  // namespace
 
 struct JitKernel {
     hipModule_t mod = nullptr;
@@ -1019,70 +1087,89 @@ int jit_code(const std::string& src, const std::string& arch, std::vector<char>*
 }
 
 std::string jit_planes_source(const Program& P, int* n_state) {
-    std::ostringstream s;
-    s << "typedef unsigned int u32;\n";
-    s << jit_step_source(P, n_state, nullptr);
-    s << kPlanesSource;
-    return s.str();
+    const Program* one[1] = {&P};
+    return jit_multi_planes_source(one, 1, n_state);
 }
 
-int jit_compile_planes(Program* P, const char* arch_in) {
-    int ns = 0;
-    const std::string src = jit_planes_source(*P, &ns);
-    if (ns > kJitPlanesMaxState)
+namespace {
+// modules are looked up by device and the programs' identities, so a launch
+// does not regenerate the source
+std::string plane_key(int dev, const Program* const* progs, int n) {
+    std::string k = std::to_string(dev);
+    for (int i = 0; i < n; ++i) k += ':' + std::to_string(progs[i]->uid);
+    return k;
+}
+}  // namespace
+
+int jit_prepare_planes(const Program* const* progs, int n, const char* arch_in, int* spill_bytes) {
+    int mx = 0;
+    const std::string src = jit_multi_planes_source(progs, n, &mx);
+    if (mx > kJitPlanesMaxState)
         return fail(RX_ETOOBIG, "the plane-form circuit keeps at most " + std::to_string(kJitPlanesMaxState) +
-                                    " state words; this program needs " + std::to_string(ns));
+                                    " state words; a program needs " + std::to_string(mx));
     std::string arch;
     int dev = -1;
     if (int rc = jit_target(arch_in, &arch, &dev)) return rc;
+    if (dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_plane_mu);
+        auto it = g_plane_mods.find(plane_key(dev, progs, n));
+        if (it != g_plane_mods.end()) {
+            if (spill_bytes) *spill_bytes = it->second->scratch;
+            return RX_OK;
+        }
+    }
     std::vector<char> code;
     if (int rc = jit_code(src, arch, &code)) return rc;
-    JitPlanes* K = new JitPlanes;
-    K->n_state = ns;
-    if (dev >= 0) {
-        hipError_t e = hipModuleLoadData(&K->mod, code.data());
-        if (e == hipSuccess) e = hipModuleGetFunction(&K->fn, K->mod, "rx_sliced_planes");
-        if (e == hipSuccess) e = hipFuncGetAttribute(&K->scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, K->fn);
-        if (e != hipSuccess) {
-            if (K->mod) hipModuleUnload(K->mod);
-            delete K;
-            return fail(RX_EHIP, std::string("plane-form kernel: ") + hipGetErrorString(e));
-        }
-        K->dev = dev;
+    if (dev < 0) return RX_OK;
+    PlaneModule* K = new PlaneModule;
+    hipError_t e = hipModuleLoadData(&K->mod, code.data());
+    if (e == hipSuccess) e = hipModuleGetFunction(&K->fn, K->mod, "rx_planes_multi");
+    if (e == hipSuccess) e = hipFuncGetAttribute(&K->scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, K->fn);
+    if (e != hipSuccess) {
+        if (K->mod) hipModuleUnload(K->mod);
+        delete K;
+        return fail(RX_EHIP, std::string("plane-form module: ") + hipGetErrorString(e));
     }
-    jit_planes_free(P);
-    P->jit_planes = K;
+    if (spill_bytes) *spill_bytes = K->scratch;
+    std::lock_guard<std::mutex> lk(g_plane_mu);
+    auto ins = g_plane_mods.emplace(plane_key(dev, progs, n), K);
+    if (!ins.second) {   // another thread loaded the same list meanwhile
+        hipModuleUnload(K->mod);
+        delete K;
+    }
     return RX_OK;
 }
 
-void jit_planes_free(Program* P) {
-    JitPlanes* K = static_cast<JitPlanes*>(P->jit_planes);
-    if (!K) return;
-    if (K->mod) hipModuleUnload(K->mod);
-    delete K;
-    P->jit_planes = nullptr;
+bool jit_planes_prepared(const Program* const* progs, int n) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lk(g_plane_mu);
+    return g_plane_mods.count(plane_key(dev, progs, n)) > 0;
 }
 
-bool jit_planes_ready(const Program* P, int* n_state, int* scratch) {
-    const JitPlanes* K = static_cast<const JitPlanes*>(P->jit_planes);
-    if (n_state) *n_state = K ? K->n_state : 0;
-    if (scratch) *scratch = K ? K->scratch : 0;
-    return K && K->fn;
-}
-
-int launch_sliced_planes(const Program* P, const uint32_t* planes, const int64_t* slab_tick, const int32_t* sorted,
-                         const int64_t* counts, int64_t max_slabs, uint8_t* out, void* stream) {
-    const JitPlanes* K = static_cast<const JitPlanes*>(P->jit_planes);
-    if (!K || !K->fn) return (int)hipErrorInvalidValue;
+int launch_planes_circuits(const Program* const* progs, int n, const uint32_t* planes, const int64_t* slab_tick,
+                           const int32_t* sorted, const int64_t* info, int64_t max_slabs, uint8_t* out,
+                           int64_t n_strings, void* stream) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return (int)hipErrorInvalidDevice;
+    PlaneModule* K = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_plane_mu);
+        auto it = g_plane_mods.find(plane_key(dev, progs, n));
+        if (it != g_plane_mods.end()) K = it->second;
+    }
+    if (!K) return -1;   // not prepared
     if (max_slabs <= 0) return 0;
+    const long long per = (max_slabs + 7) / 8;
+    const unsigned grid = (unsigned)(8 * per * n);
     const void* a0 = planes;
     const void* a1 = slab_tick;
     const void* a2 = sorted;
-    const void* a3 = counts;
+    const void* a3 = info;
     void* a4 = out;
-    void* args[] = {&a0, &a1, &a2, &a3, &a4};
-    return (int)hipModuleLaunchKernel(K->fn, (unsigned)max_slabs, 1, 1, 64, 1, 1, 0, (hipStream_t)stream, args,
-                                      nullptr);
+    long long a5 = n_strings;
+    void* args[] = {&a0, &a1, &a2, &a3, &a4, &a5};
+    return (int)hipModuleLaunchKernel(K->fn, grid, 1, 1, 64, 1, 1, 0, (hipStream_t)stream, args, nullptr);
 }
 
 int jit_compile(Program* P, const char* arch_in) {

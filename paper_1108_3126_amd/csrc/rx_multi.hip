@@ -568,11 +568,10 @@ int launch_planes_multi(const PlaneMultiArgs& m) {
     pa.planes = planes;
     hipLaunchKernelGGL(k_planes, dim3(m.plane_grid), dim3(256), 0, st, pa);
     if (hipError_t e = hipGetLastError()) return (int)e;
-    // every program's circuit over the slabs
-    for (int i = 0; i < m.n_progs; ++i)
-        if (int e = launch_sliced_planes(m.progs[i], planes, a.slab_tick, a.sorted, a.info, S, m.out + (int64_t)i * m.n,
-                                         m.stream))
-            return e;
+    // every (program, slab) pair in one launch
+    if (int e = launch_planes_circuits(m.progs, m.n_progs, planes, a.slab_tick, a.sorted, a.info, S, m.out, m.n,
+                                       m.stream))
+        return e;
     // strings too long for a slab: table form, every program
     OverArgs o;
     o.info = a.info;

@@ -172,7 +172,6 @@ Server::~Server() {
     if (d_arena) hipFree(d_arena);
     for (auto& kv : cache) {
         jit_free(kv.second->prog);
-        jit_planes_free(kv.second->prog);
         delete kv.second->prog;
         delete kv.second;
     }

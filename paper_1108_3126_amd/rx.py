@@ -104,9 +104,8 @@ SIGNATURES = {
     "rx_program_jit_stats": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "rx_program_jit_staging": (ctypes.c_int, [_VP, ctypes.POINTER(_I32)]),
     "rx_program_jit_guard": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
-    "rx_program_jit_planes": (ctypes.c_int, [_VP, ctypes.c_char_p]),
+    "rx_match_multi_prepare": (ctypes.c_int, [ctypes.POINTER(_VP), _I32, ctypes.c_char_p, ctypes.POINTER(_I32)]),
     "rx_program_jit_planes_source": (ctypes.c_int, [_VP, ctypes.c_char_p, _SZ, ctypes.POINTER(_SZ)]),
-    "rx_program_planes_info": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "rx_isa_check_staging": (ctypes.c_int, [ctypes.c_char_p, _SZ, ctypes.c_char_p, ctypes.c_char_p,
                                             ctypes.POINTER(_I32)]),
     "rx_match_first": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _VP]),
@@ -271,16 +270,6 @@ class Program:
         """Generate and compile the bit-sliced circuit kernel (hiprtc)."""
         _check(lib().rx_program_jit(self._h, arch.encode() if arch else None))
         return self
-
-    def jit_planes(self, arch=None):
-        """Generate and compile the plane-form circuit (strings of any length, rx_match_multi RX_FORM_PLANES)."""
-        _check(lib().rx_program_jit_planes(self._h, arch.encode() if arch else None))
-        return self
-
-    def planes_info(self):
-        r, ns, sp = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().rx_program_planes_info(self._h, ctypes.byref(r), ctypes.byref(ns), ctypes.byref(sp)))
-        return {"ready": r.value, "state_words": ns.value, "spill_bytes": sp.value}
 
     def jit_planes_source(self) -> str:
         n = ctypes.c_size_t()
@@ -532,6 +521,15 @@ def match_fixed(prog: Program, data, length: int, n: int = None, out=None, launc
         _check(lib().rx_match_fixed_ex(prog.handle, ctypes.c_void_p(data.data_ptr()), int(length), int(n),
                                        ctypes.c_void_p(out.data_ptr()), ctypes.byref(L), sh))
     return out
+
+
+def prepare_multi(progs, arch=None) -> int:
+    """Compile and load the plane-form module of this program list (rx_match_multi_prepare); returns the
+    per-lane spill bytes the device compiler chose (0 when every state word fits in registers)."""
+    handles = (ctypes.c_void_p * len(progs))(*[p.handle.value for p in progs])
+    sp = ctypes.c_int32()
+    _check(lib().rx_match_multi_prepare(handles, len(progs), arch.encode() if arch else None, ctypes.byref(sp)))
+    return sp.value
 
 
 def match_multi(progs, data, offsets, out=None, config=None, work=None, stream=None):

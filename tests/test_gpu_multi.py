@@ -74,9 +74,7 @@ def test_multi_edge_cases(dev):
 
 # -- plane form: the bit-sliced circuit over length-sorted slabs -----------------
 def _planes(rx, ps):
-    for p in ps:
-        p.jit_planes()
-        assert p.planes_info()["ready"] == 1
+    rx.prepare_multi(ps)
     return rx.multi_config(form=rx.FORM_PLANES)
 
 
@@ -122,6 +120,23 @@ def test_planes_edge_cases(dev):
     z = rx.match_multi(ps, torch.zeros(1, dtype=torch.uint8, device=dev), torch.zeros(1, dtype=torch.int64, device=dev),
                        config=cfg)
     assert z.shape == (4, 0)
+
+
+def test_planes_needs_a_prepared_list(dev, multi_case):
+    from paper_1108_3126_amd import rx
+
+    progs, s, want = multi_case
+    ps = [rx.compile(p.ast, p.root, p.classes, p.search).upload(dev) for p in progs[:2]]
+    d, o = torch.from_numpy(s.data).to(dev), torch.from_numpy(s.offsets).to(dev)
+    with pytest.raises(rx.RxError) as ei:
+        rx.match_multi(ps, d, o, config=rx.multi_config(form=rx.FORM_PLANES))
+    assert ei.value.code == rx.RX_EINVAL
+    rx.prepare_multi(ps)
+    # a different order is another list
+    with pytest.raises(rx.RxError):
+        rx.match_multi(ps[::-1], d, o, config=rx.multi_config(form=rx.FORM_PLANES))
+    got = rx.match_multi(ps, d, o, config=rx.multi_config(form=rx.FORM_PLANES)).cpu().numpy()
+    assert np.array_equal(got, want[:2])
 
 
 def test_planes_repeat_calls_share_workspace(dev, multi_case):

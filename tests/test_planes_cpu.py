@@ -146,9 +146,9 @@ extern "C" void run_planes(const uint8_t* bytes, const int64_t* lo, const int64_
         for (int64_t k = 0; k < count; ++k) if (len[s0 + k] > mx) mx = len[s0 + k];
         const int64_t ticks = (mx + 3) / 4;
         for (int lane = 0; lane < 64; ++lane) {
-            u32 st[RX_NS];
+            u32 st[RxProg0::NS];
             u32 acc;
-            rx_init(st, acc);
+            RxProg0::init(st, acc);
             u32 accf = acc;
             for (int64_t c = 0; 4 * c < ticks; ++c) {
                 uint32_t win[32][4];
@@ -162,7 +162,7 @@ extern "C" void run_planes(const uint8_t* bytes, const int64_t* lo, const int64_
                 for (int kk = 0; kk < 4 && 4 * c + kk < ticks; ++kk) {
                     u32 w[36];
                     rx::planes_tick(win, L, kk, 4 * (4 * c + kk), 0, w);
-                    rx_planes_tick(st, acc, accf, w);
+                    rx_planes_tick<RxProg0>(st, acc, accf, w);
                 }
             }
             for (int j = 0; j < 32; ++j) {
