@@ -592,9 +592,6 @@ int match_multi_planes(const rx_program* const* progs, int32_t n_progs, const ui
     m.n_progs = n_progs;
     m.block_lines = shape.block_lines;
     m.item_grid = shape.grid;
-    int cus = 0;
-    if (hip_cu_count(&cus) || cus <= 0) cus = 256;
-    m.plane_grid = 4 * cus;
     m.bytes = d_bytes;
     m.offsets = d_offsets;
     m.n = n;

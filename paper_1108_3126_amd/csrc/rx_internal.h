@@ -124,7 +124,7 @@ struct PlaneMultiArgs {
     ProgDesc descs[kMaxItemProgs];         // device tables (strings too long for a slab)
     int32_t n_progs;
     int32_t block_lines;                   // table-form item size
-    int32_t plane_grid, item_grid;
+    int32_t item_grid;
     const uint8_t* bytes;
     const int64_t* offsets;
     int64_t n;
@@ -206,8 +206,7 @@ int jit_prepare_planes(const Program* const* progs, int n, const char* arch, int
 bool jit_planes_prepared(const Program* const* progs, int n);
 // One wavefront per (program, slab); returns -1 when the list was not prepared.
 int launch_planes_circuits(const Program* const* progs, int n, const uint32_t* planes, const int64_t* slab_tick,
-                           const int32_t* sorted, const int64_t* info, int64_t max_slabs, uint8_t* out,
-                           int64_t n_strings, void* stream);
+                           const int64_t* info, uint32_t* res, int64_t max_slabs, void* stream);
 // Static check of a register-staged kernel in a code object (rx_isa_guard.cpp):
 // *violations = instructions not written by the kernel itself that name an
 // accumulation register.  Returns 0 when the check ran, < 0 when it could not.

@@ -880,11 +880,10 @@ const char* kPlanesKernelSource = R"RX(
 // ---- device kernel ----
 typedef unsigned int rx_pv4 __attribute__((ext_vector_type(4)));
 // Slab s (ticks slab_tick[s] .. slab_tick[s+1] of `planes`) for program PR;
-// sorted[s * 2048 + k] is the string the slab's k-th entry stands for.
+// lane l writes its 32 results (bit j: the slab's entry 64 j + l) to res[l].
 template <class PR>
 __device__ __forceinline__ void rx_run_slab(const u32* __restrict__ planes, const long long* __restrict__ slab_tick,
-                                            const int* __restrict__ sorted, long long n_sliced, long long s,
-                                            unsigned char* __restrict__ out) {
+                                            long long s, u32* __restrict__ res) {
     const int lane = threadIdx.x;
     const long long t0 = slab_tick[s], T = slab_tick[s + 1] - t0;
     const rx_pv4* p = reinterpret_cast<const rx_pv4*>(planes) + t0 * (9 * 64) + lane;
@@ -913,20 +912,16 @@ __device__ __forceinline__ void rx_run_slab(const u32* __restrict__ planes, cons
 #pragma unroll
         for (int q = 0; q < 9; ++q) cur[q] = nxt[q];
     }
-#pragma unroll
-    for (int j = 0; j < 32; ++j) {
-        const long long k = s * 2048 + j * 64 + lane;
-        if (k < n_sliced) out[sorted[k]] = (unsigned char)((accf >> j) & 1u);
-    }
+    res[lane] = accf;   // one coalesced word per lane
 }
 
 // One wavefront per (program, slab).  Workgroup b runs on XCD b mod 8; its
 // slab rank (0 = longest) is 8 * ((b / 8) / n_progs) + b mod 8 and its
-// program (b / 8) mod n_progs.  info[0] = strings in slabs; results of
-// program p go to out[p * n + string].
+// program (b / 8) mod n_progs.  info[0] = strings in slabs; the results of
+// program p and slab s go to res[(p * max_slabs + s) * 64 .. + 64).
 extern "C" __global__ __launch_bounds__(64) void rx_planes_multi(const u32* __restrict__ planes,
-        const long long* __restrict__ slab_tick, const int* __restrict__ sorted, const long long* __restrict__ info,
-        unsigned char* __restrict__ out, long long n) {
+        const long long* __restrict__ slab_tick, const long long* __restrict__ info, u32* __restrict__ res,
+        long long max_slabs) {
     const long long b = blockIdx.x;
     const long long k = b >> 3;
     const int p = (int)(k % RX_NPROGS);
@@ -934,7 +929,9 @@ extern "C" __global__ __launch_bounds__(64) void rx_planes_multi(const u32* __re
     const long long n_sliced = info[0];
     const long long S = (n_sliced + 2047) / 2048;
     if (r >= S) return;
-    rx_dispatch(p, planes, slab_tick, sorted, n_sliced, S - 1 - r, out + p * n);
+    // the longest slabs set the kernel's length: their wavefronts issue first on their SIMDs
+    if (r < 16) __builtin_amdgcn_s_setprio(3);
+    rx_dispatch(p, planes, slab_tick, S - 1 - r, res + (p * max_slabs + (S - 1 - r)) * 64);
 }
 )RX";
 
@@ -966,10 +963,9 @@ std::string jit_multi_planes_source(const Program* const* progs, int n, int* max
     std::ostringstream disp;
     disp << kern.substr(0, kern.find("extern \"C\""));
     disp << "__device__ __forceinline__ void rx_dispatch(int p, const u32* __restrict__ planes, const long long* "
-            "__restrict__ slab_tick, const int* __restrict__ sorted, long long n_sliced, long long s, unsigned char* "
-            "__restrict__ out) {\n    switch (p) {\n";
+            "__restrict__ slab_tick, long long s, u32* __restrict__ res) {\n    switch (p) {\n";
     for (int k = 0; k < n; ++k)
-        disp << "    case " << k << ": rx_run_slab<RxProg" << k << ">(planes, slab_tick, sorted, n_sliced, s, out); break;\n";
+        disp << "    case " << k << ": rx_run_slab<RxProg" << k << ">(planes, slab_tick, s, res); break;\n";
     disp << "    default: break;\n    }\n}\n";
     disp << kern.substr(kern.find("extern \"C\""));
     (void)at;
@@ -1148,8 +1144,7 @@ bool jit_planes_prepared(const Program* const* progs, int n) {
 }
 
 int launch_planes_circuits(const Program* const* progs, int n, const uint32_t* planes, const int64_t* slab_tick,
-                           const int32_t* sorted, const int64_t* info, int64_t max_slabs, uint8_t* out,
-                           int64_t n_strings, void* stream) {
+                           const int64_t* info, uint32_t* res, int64_t max_slabs, void* stream) {
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return (int)hipErrorInvalidDevice;
     PlaneModule* K = nullptr;
@@ -1164,11 +1159,10 @@ int launch_planes_circuits(const Program* const* progs, int n, const uint32_t* p
     const unsigned grid = (unsigned)(8 * per * n);
     const void* a0 = planes;
     const void* a1 = slab_tick;
-    const void* a2 = sorted;
-    const void* a3 = info;
-    void* a4 = out;
-    long long a5 = n_strings;
-    void* args[] = {&a0, &a1, &a2, &a3, &a4, &a5};
+    const void* a2 = info;
+    void* a3 = res;
+    long long a4 = max_slabs;
+    void* args[] = {&a0, &a1, &a2, &a3, &a4};
     return (int)hipModuleLaunchKernel(K->fn, grid, 1, 1, 64, 1, 1, 0, (hipStream_t)stream, args, nullptr);
 }
 

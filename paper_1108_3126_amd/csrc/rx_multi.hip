@@ -283,13 +283,16 @@ struct SortArgs {
     int32_t* counts;   // [kSortBins]
     int32_t* cursor;   // [kSortBins]
     int32_t* start;    // [kSortBins + 1]
-    int64_t* info;     // [0] strings in slabs, [1] longer strings, [2] plane chunks (16 positions of a slab)
+    int64_t* info;     // [0] strings in slabs, [1] longer strings, [2] plane-kernel groups, [3] capacity exceeded
     int32_t* sorted;   // [n]: slab strings by length, then the longer ones
+    int32_t* rank;     // [n]: where each string went in `sorted`
     int64_t* slab_tick;   // [max_slabs + 1]
     int64_t* slab_chunk;  // [max_slabs + 1]
     int64_t max_slabs;
     int64_t tick_cap;     // ticks the plane buffer holds
 };
+
+constexpr int kGroupTicks = 64;   // plane-kernel work unit: 256 positions of one slab
 
 __device__ __forceinline__ int sort_bin(int64_t len) { return len < kSortBins - 1 ? (int)len : kSortBins - 1; }
 
@@ -360,12 +363,13 @@ __global__ __launch_bounds__(256) void k_sort_scatter(SortArgs a) {
         const int b = sort_bin(a.offsets[i + 1] - a.offsets[i]);
         const int32_t pos = atomicAdd(&h[b], 1);
         a.sorted[a.start[b] + g[b] + pos] = (int32_t)i;
+        a.rank[i] = a.start[b] + g[b] + pos;
     }
 }
 
 // One workgroup of 1024 threads: ticks of every slab (its longest string is
-// its last), their prefix sums, and the 16-position chunks the plane kernel
-// works in.  If the total would pass the plane buffer's capacity (only when
+// its last), their prefix sums, and the groups of kGroupTicks ticks the plane
+// kernel works in (slab_chunk: prefix sums of groups).  If the total would pass the plane buffer's capacity (only when
 // the caller's byte bound is below the real total), every slab gets no ticks:
 // nothing is read or written past the buffer, and info[3] is set.
 __global__ __launch_bounds__(1024) void k_slab_scan(SortArgs a) {
@@ -385,7 +389,7 @@ __global__ __launch_bounds__(1024) void k_slab_scan(SortArgs a) {
         if (s0 + k < S) {
             const int64_t t = ticks_of(s0 + k);
             sum += t;
-            csum += (t + 3) / 4;
+            csum += (t + kGroupTicks - 1) / kGroupTicks;
         }
     part[threadIdx.x] = sum;
     cpart[threadIdx.x] = csum;
@@ -406,7 +410,7 @@ __global__ __launch_bounds__(1024) void k_slab_scan(SortArgs a) {
             a.slab_chunk[s0 + k] = over ? 0 : crun;
             const int64_t t = ticks_of(s0 + k);
             run += t;
-            crun += (t + 3) / 4;
+            crun += (t + kGroupTicks - 1) / kGroupTicks;
         }
     if (threadIdx.x == 1023) {
         a.slab_tick[S] = over ? 0 : part[1023];
@@ -426,41 +430,55 @@ struct PlanesArgs {
     uint32_t* planes;
 };
 
-// Gathers and transposes: one wavefront per (slab, 16 positions), persistent.
-// Lane l reads a 16-byte window of each of its 32 strings, then writes four
-// ticks of plane words (coalesced: 1 KiB per group of four words).
-__global__ __launch_bounds__(256) void k_planes(PlanesArgs a) {
-    const int lane = threadIdx.x & 63;
+// Gathers and transposes: one workgroup per group of kGroupTicks ticks of a
+// slab (longest slabs first), its four wavefronts on 16-position chunks c =
+// wave, wave + 4, ... of the group, so the four read the same cache lines of
+// the slab's strings at about the same time.  Lane l reads a 16-byte window
+// of each of its 32 strings and writes four ticks of plane words (1 KiB per
+// group of four words, coalesced).  A slab of n ticks takes n / kGroupTicks
+// workgroups, so the longest slabs do not serialise the kernel.
+__global__ __launch_bounds__(256, 2) void k_planes(PlanesArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t n_sliced = a.info[0];
     const int64_t S = (n_sliced + kSlabStrings - 1) / kSlabStrings;
-    const int64_t chunks = a.info[2];
-    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g < chunks; g += waves) {
-        // the slab holding chunk g: the last s with slab_chunk[s] <= g
-        int64_t lo = 0, hi = S - 1;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi + 1) >> 1;
-            if (a.slab_chunk[mid] <= g) lo = mid;
-            else hi = mid - 1;
+    const int64_t groups = a.info[2];
+    const int64_t u = groups - 1 - (int64_t)blockIdx.x;   // the last groups belong to the longest slabs
+    if (u < 0) return;
+    // the slab holding group u: the last s with slab_chunk[s] <= u
+    int64_t lo = 0, hi = S - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (a.slab_chunk[mid] <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t s = lo;
+    const int64_t g = u - a.slab_chunk[s];
+    const int64_t t_base = a.slab_tick[s], T = a.slab_tick[s + 1] - t_base;
+    const int64_t first = a.sorted[s * kSlabStrings];
+    const int64_t minlen = a.offsets[first + 1] - a.offsets[first];
+    // where the slab's strings are, once per workgroup (the four wavefronts share them)
+    __shared__ int64_t s_lo[kSlabStrings];
+    __shared__ int32_t s_len[kSlabStrings];
+    for (int k = threadIdx.x; k < kSlabStrings; k += blockDim.x) {
+        const int64_t e = s * kSlabStrings + k;
+        int64_t o = 0, n = 0;
+        if (e < n_sliced) {
+            const int32_t id = a.sorted[e];
+            o = a.offsets[id];
+            n = a.offsets[id + 1] - o;
         }
-        const int64_t s = lo;
-        const int64_t c = g - a.slab_chunk[s];
-        const int64_t t_base = a.slab_tick[s], T = a.slab_tick[s + 1] - t_base;
-        const int64_t first = a.sorted[s * kSlabStrings];
-        const int64_t minlen = a.offsets[first + 1] - a.offsets[first];
+        s_lo[k] = o;
+        s_len[k] = (int32_t)n;   // slab strings are shorter than kSortBins
+    }
+    __syncthreads();
+    const int64_t c_end = (g + 1) * (kGroupTicks / 4) < (T + 3) / 4 ? (g + 1) * (kGroupTicks / 4) : (T + 3) / 4;
+    for (int64_t c = g * (kGroupTicks / 4) + wave; c < c_end; c += 4) {
         uint32_t win[32][4];
-        int64_t len[32];
+        int32_t len[32];
 #pragma unroll
         for (int j = 0; j < 32; ++j) {
-            const int64_t k = s * kSlabStrings + j * 64 + lane;
-            int64_t lo_b = 0, ln = 0;
-            if (k < n_sliced) {
-                const int32_t id = a.sorted[k];
-                lo_b = a.offsets[id];
-                ln = a.offsets[id + 1] - lo_b;
-            }
-            len[j] = ln;
-            planes_window16(a.bytes + lo_b, ln, 16 * c, win[j]);
+            len[j] = s_len[j * 64 + lane];
+            planes_window16(a.bytes + s_lo[j * 64 + lane], len[j], 16 * c, win[j]);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -472,6 +490,32 @@ __global__ __launch_bounds__(256) void k_planes(PlanesArgs a) {
 #pragma unroll
             for (int q = 0; q < 9; ++q) dst[q * 64] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
         }
+    }
+}
+
+// Results back in the strings' own order: string i went to sorted position
+// rank[i] (slab r / 2048, entry r % 2048 = 64 j + l: bit j of lane l's word).
+// One thread per string and program, consecutive threads on consecutive
+// strings, so the result bytes are written in order; strings too long for a
+// slab are left to the table-form kernel.
+struct GatherArgs {
+    const int32_t* rank;
+    const int64_t* info;
+    const uint32_t* res;
+    int64_t max_slabs, n;
+    uint8_t* out;
+};
+
+__global__ __launch_bounds__(256) void k_gather_out(GatherArgs a) {
+    const int64_t n_sliced = a.info[0];
+    const int64_t p = blockIdx.y;
+    const uint32_t* res = a.res + p * a.max_slabs * 64;
+    uint8_t* out = a.out + p * a.n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = a.rank[i];
+        if (r >= n_sliced) continue;
+        const int64_t k = r & (kSlabStrings - 1);
+        out[i] = (uint8_t)((res[(r >> 11) * 64 + (k & 63)] >> (k >> 6)) & 1u);
     }
 }
 
@@ -520,9 +564,9 @@ int64_t plane_workspace_bytes(int64_t n, int64_t max_bytes, int32_t n_progs, int
     auto al = [](int64_t x) { return (x + 255) & ~int64_t(255); };
     if (block_lines <= 0) block_lines = 256;
     const int64_t S = plane_max_slabs(n);
-    return al(4 * (3 * (int64_t)kSortBins + 1)) + al(8 * 8) + al(4 * n) + 2 * al(8 * (S + 1)) + al(8 * 4) +
+    return al(4 * (3 * (int64_t)kSortBins + 1)) + al(8 * 8) + 2 * al(4 * n) + 2 * al(8 * (S + 1)) + al(8 * 4) +
            al((int64_t)sizeof(WorkItem) * (int64_t)n_progs * (n / block_lines + 1)) +
-           al(plane_tick_cap(n, max_bytes) * kPlaneTickWords * 64 * 4);
+           al(4 * 64 * S * (int64_t)n_progs) + al(plane_tick_cap(n, max_bytes) * kPlaneTickWords * 64 * 4);
 }
 
 int launch_planes_multi(const PlaneMultiArgs& m) {
@@ -541,6 +585,8 @@ int launch_planes_multi(const PlaneMultiArgs& m) {
     w += al(8 * 8);
     a.sorted = reinterpret_cast<int32_t*>(w);
     w += al(4 * m.n);
+    a.rank = reinterpret_cast<int32_t*>(w);
+    w += al(4 * m.n);
     a.slab_tick = reinterpret_cast<int64_t*>(w);
     w += al(8 * (S + 1));
     a.slab_chunk = reinterpret_cast<int64_t*>(w);
@@ -549,6 +595,8 @@ int launch_planes_multi(const PlaneMultiArgs& m) {
     w += al(8 * 4);
     WorkItem* items = reinterpret_cast<WorkItem*>(w);
     w += al((int64_t)sizeof(WorkItem) * (int64_t)m.n_progs * (m.n / m.block_lines + 1));
+    uint32_t* res = reinterpret_cast<uint32_t*>(w);
+    w += al(4 * 64 * S * (int64_t)m.n_progs);
     uint32_t* planes = reinterpret_cast<uint32_t*>(w);
     a.max_slabs = S;
     a.tick_cap = plane_tick_cap(m.n, m.max_bytes);
@@ -566,12 +614,19 @@ int launch_planes_multi(const PlaneMultiArgs& m) {
     pa.slab_tick = a.slab_tick;
     pa.slab_chunk = a.slab_chunk;
     pa.planes = planes;
-    hipLaunchKernelGGL(k_planes, dim3(m.plane_grid), dim3(256), 0, st, pa);
+    hipLaunchKernelGGL(k_planes, dim3((unsigned)(a.tick_cap / kGroupTicks + S + 1)), dim3(256), 0, st, pa);
     if (hipError_t e = hipGetLastError()) return (int)e;
-    // every (program, slab) pair in one launch
-    if (int e = launch_planes_circuits(m.progs, m.n_progs, planes, a.slab_tick, a.sorted, a.info, S, m.out, m.n,
-                                       m.stream))
-        return e;
+    // every (program, slab) pair in one launch, then the results in string order
+    if (int e = launch_planes_circuits(m.progs, m.n_progs, planes, a.slab_tick, a.info, res, S, m.stream)) return e;
+    GatherArgs ga;
+    ga.rank = a.rank;
+    ga.info = a.info;
+    ga.res = res;
+    ga.max_slabs = S;
+    ga.n = m.n;
+    ga.out = m.out;
+    const unsigned gx = (unsigned)((m.n + 255) / 256 < 2048 ? (m.n + 255) / 256 : 2048);
+    hipLaunchKernelGGL(k_gather_out, dim3(gx, (unsigned)m.n_progs), dim3(256), 0, st, ga);
     // strings too long for a slab: table form, every program
     OverArgs o;
     o.info = a.info;

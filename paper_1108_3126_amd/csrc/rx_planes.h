@@ -108,7 +108,8 @@ RX_PL_DEV void planes_window16(const uint8_t* s, int64_t len, int64_t off, uint3
 }
 
 // The strings of a slab whose length exceeds position p: bit j for len[j] > p.
-RX_PL_DEV uint32_t planes_valid(const int64_t (&len)[32], int64_t p) {
+template <class LT>
+RX_PL_DEV uint32_t planes_valid(const LT (&len)[32], int64_t p) {
     uint32_t v = 0;
 #pragma unroll
     for (int j = 0; j < 32; ++j) v |= (len[j] > p ? 1u : 0u) << j;
@@ -118,7 +119,8 @@ RX_PL_DEV uint32_t planes_valid(const int64_t (&len)[32], int64_t p) {
 // Tick words of one lane from the 16-byte windows of its 32 strings: tick k
 // (0..3) of the windows, i.e. positions off + 4k .. off + 4k + 3.  minlen is
 // a lower bound of every length (whole words of ones below it).
-RX_PL_DEV void planes_tick(const uint32_t (&win)[32][4], const int64_t (&len)[32], int k, int64_t pos0,
+template <class LT>
+RX_PL_DEV void planes_tick(const uint32_t (&win)[32][4], const LT (&len)[32], int k, int64_t pos0,
                            int64_t minlen, uint32_t (&out)[kPlaneTickWords]) {
     uint32_t x[32];
 #pragma unroll
