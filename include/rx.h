@@ -220,7 +220,11 @@ typedef struct {
                                for half of the strings, that half running 32 bytes behind the other so the two
                                waves' requests alternate (default).  A program whose staged kernels (1, 3, 4,
                                5) would spill registers runs 2 instead; 5 needs length <= 2^26 (else 4).
-                               0 = 5 when its kernel was kept, else 3, else 2. */
+                               0 = 5 when its kernel was kept, else 3, else 2.
+                               wave: wavefronts per string, 1, 2 or 4 (each takes every 2nd or 4th
+                               survivor word and the partial next sets meet in LDS once per byte);
+                               0 = 4 when the strings number at most a quarter of the SIMDs, 2 when at
+                               most half, else 1. */
 } rx_launch;
 
 /* Earliest accepting prefix (the accept bit's first appearance, Def. 5.3

@@ -79,19 +79,21 @@ def tune_single(prog: rx.Program, data, offsets=None, length=0, n=None, budget_r
     return best, dict(rec, cached=False)
 
 
-def tune_multi(progs, data, offsets, budget_runs=96, cache_path=None, use_cache=True):
-    """Best rx_multi_config for rx_match_multi.  Returns (config, info dict)."""
+def tune_multi(progs, data, offsets, budget_runs=96, cache_path=None, use_cache=True, planes=False):
+    """Best rx_multi_config for rx_match_multi.  Returns (config, info dict).  planes: also try the
+    plane form (the list must be prepared with rx.prepare_multi)."""
     import torch
 
     cache_path = cache_path or DEFAULT_CACHE
     n = offsets.numel() - 1
     mean_len = float((offsets[-1] - offsets[0]).item()) / max(n, 1)
     lmax = max(p.info.n_leaves for p in progs)
-    key = f"{_arch()}|multi|P{len(progs)}|L{_cls(lmax)}|len{_cls(mean_len)}|n{_cls(n)}"
+    key = f"{_arch()}|multi|P{len(progs)}|L{_cls(lmax)}|len{_cls(mean_len)}|n{_cls(n)}|planes{int(planes)}"
     cache = _load(cache_path) if use_cache else {}
     if key in cache:
         c = cache[key]
-        return rx.multi_config(c["edges"], c["block"], c["grid"]), dict(c, cached=True)
+        return rx.multi_config(c["edges"], c["block"], c["grid"], c.get("form", 0), c.get("max_bytes", 0)), \
+            dict(c, cached=True)
     for p in progs:
         if p._dev_buf is None:
             p.upload(device=offsets.device)
@@ -99,6 +101,10 @@ def tune_multi(progs, data, offsets, budget_runs=96, cache_path=None, use_cache=
     need = rx.lib().rx_match_multi_workspace(n, len(progs), ctypes.byref(worst))
     if need < 0:
         rx._check(int(need))
+    if planes:
+        # room for the plane form too (the tuner tries it when the list has its module)
+        pc = rx.multi_config(form=rx.FORM_PLANES, max_bytes=int((offsets[-1] - offsets[0]).item()))
+        need = max(need, rx.lib().rx_match_multi_workspace(n, len(progs), ctypes.byref(pc)))
     work = torch.empty(int(need) + 256, dtype=torch.uint8, device=offsets.device)
     wptr = work.data_ptr() + ((-work.data_ptr()) % 256)
     out = torch.empty((len(progs), n), dtype=torch.uint8, device=offsets.device)
@@ -111,7 +117,7 @@ def tune_multi(progs, data, offsets, budget_runs=96, cache_path=None, use_cache=
                                          ctypes.c_void_p(wptr), int(need), int(budget_runs), ctypes.byref(best),
                                          ctypes.byref(ms), ctypes.byref(nc), rx._stream_handle()))
     rec = {"edges": [best.edges[i] for i in range(best.n_edges)], "block": best.block, "grid": best.grid,
-           "ms": ms.value, "candidates": nc.value}
+           "form": best.form, "max_bytes": best.max_bytes, "ms": ms.value, "candidates": nc.value}
     cache[key] = rec
     _store(cache_path, cache)
     return best, dict(rec, cached=False)

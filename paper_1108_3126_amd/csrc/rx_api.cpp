@@ -187,6 +187,8 @@ int rx_match_ex(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d
         break;
     case RX_VARIANT_WAVE:
         if (P->W > kWaveMaxWords) return fail(RX_ETOOBIG, "the wavefront kernel holds sets of at most 128 words");
+        if (a.unroll != 0 && a.unroll != 1 && a.unroll != 2 && a.unroll != 4)
+            return fail(RX_EINVAL, "wavefronts per string (unroll) must be 0 (by string count), 1, 2 or 4");
         e = launch_wave(a);
         break;
     default: return fail(RX_EINVAL, "unknown or unavailable kernel variant");
@@ -504,6 +506,8 @@ int rx_match_fixed_ex(const rx_program* prog, const uint8_t* d_bytes, int64_t le
         break;
     case RX_VARIANT_WAVE:
         if (P->W > kWaveMaxWords) return fail(RX_ETOOBIG, "the wavefront kernel holds sets of at most 128 words");
+        if (a.unroll != 0 && a.unroll != 1 && a.unroll != 2 && a.unroll != 4)
+            return fail(RX_EINVAL, "wavefronts per string (unroll) must be 0 (by string count), 1, 2 or 4");
         e = launch_wave(a);
         break;
     default: return fail(RX_EINVAL, "unknown kernel variant");

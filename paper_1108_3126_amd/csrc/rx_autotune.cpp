@@ -122,6 +122,11 @@ int autotune_single(const Program* P, const uint8_t* d_bytes, const int64_t* d_o
             for (int gm : {0, 2, 4, 8}) add(RX_VARIANT_LANE, block, gm * cus);
     for (int block : {64, 256, 1024})
         for (int gm : {0, 4}) add(RX_VARIANT_WAVE, block, gm * cus);
+    // lanes per set: 64 (one wavefront per string), 128 or 256 (two or four wavefronts per string)
+    for (int ws : {2, 4}) {
+        add(RX_VARIANT_WAVE, 0, 0);
+        cands.back().launch.unroll = ws;
+    }
     if (n_cands) *n_cands = (int)cands.size();
     auto run = [&](const Cand& c) -> int {
         return fixed ? rx_match_fixed_ex(reinterpret_cast<const rx_program*>(P), d_bytes, length, n, d_out, &c.launch, stream)
@@ -158,6 +163,23 @@ int autotune_multi(const rx_program* const* progs, int32_t n_progs, const uint8_
                 c.multi.grid = gm * cus;
                 cands.push_back(c);
             }
+    // the plane form (bit-sliced circuits), when the list has its module and the workspace holds the planes
+    if (n > 0) {
+        std::vector<const Program*> ps(n_progs);
+        for (int i = 0; i < n_progs; ++i) ps[i] = reinterpret_cast<const Program*>(progs[i]);
+        int64_t ends[2] = {0, 0};
+        if (jit_planes_prepared(ps.data(), n_progs) &&
+            hipMemcpy(&ends[0], d_offsets, 8, hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(&ends[1], d_offsets + n, 8, hipMemcpyDeviceToHost) == hipSuccess) {
+            const int64_t total = ends[1] - ends[0];
+            if (total >= 0 && plane_workspace_bytes(n, total, n_progs, 256) <= (int64_t)work_bytes) {
+                Cand c;
+                c.multi.form = RX_FORM_PLANES;
+                c.multi.max_bytes = total;
+                cands.push_back(c);
+            }
+        }
+    }
     if (n_cands) *n_cands = (int)cands.size();
     auto run = [&](const Cand& c) -> int {
         return rx_match_multi(progs, n_progs, d_bytes, d_offsets, n, d_out, d_work, work_bytes, &c.multi, stream);

@@ -283,6 +283,113 @@ __global__ __launch_bounds__(1024) void k_wave(KArgs a) {
     }
 }
 
+// One workgroup of WS wavefronts per string, for large sets and few strings
+// (otherwise most SIMDs would sit idle).  Every wavefront keeps the whole set
+// (lane j: words j and j + 64); per byte each takes the survivor words whose
+// index is its own modulo WS, ORs their Follow rows (or chunk-union rows)
+// into a partial next set, and the partials meet in LDS: the union of the
+// images of a set's pointers is the image of the set (Def. 5.1).  One barrier
+// per byte (the partials alternate between two LDS buffers).
+template <bool TABLES_IN_LDS, int WS>
+__global__ __launch_bounds__(64 * WS) void k_wave_split(KArgs a) {
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t part[2][WS][kWaveMaxWords];
+    const int W = a.W, L = a.L;
+    const uint32_t* M = a.bytemask;
+    const uint32_t* F = a.follow;
+    if (TABLES_IN_LDS) {
+        uint32_t* Ml = lds;
+        uint32_t* Fl = lds + 256 * W;
+        for (int i = threadIdx.x; i < 256 * W; i += blockDim.x) Ml[i] = a.bytemask[i];
+        for (int i = threadIdx.x; i < L * W; i += blockDim.x) Fl[i] = a.follow[i];
+        __syncthreads();
+        M = Ml;
+        F = Fl;
+    }
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool own0 = lane < W, own1 = lane + 64 < W;
+    const int aw = L >> 5;
+    const uint32_t abit = 1u << (L & 31);
+    // survivor words this wavefront takes: word index (lane + 64 half) % WS == wave
+    uint64_t mine[2] = {0, 0};
+    for (int l = 0; l < 64; ++l) {
+        if ((l % WS) == wave) mine[0] |= 1ull << l;
+        if (((l + 64) % WS) == wave) mine[1] |= 1ull << l;
+    }
+    int parity = 0;
+    for (int64_t sid = blockIdx.x; sid < a.n; sid += gridDim.x) {
+        uint32_t S0 = own0 ? a.first[lane] : 0u;
+        uint32_t S1 = own1 ? a.first[lane + 64] : 0u;
+        const int64_t lo = a.offsets ? a.offsets[sid] : sid * a.stride;
+        const int64_t hi = a.offsets ? a.offsets[sid + 1] : lo + a.stride;
+        int res = -1;
+        const int64_t skew = (int64_t)(reinterpret_cast<uintptr_t>(a.bytes) & 3);
+        for (int64_t base = ((lo + skew) & ~int64_t(3)) - skew; base < hi && res < 0; base += 4) {
+            const uint32_t word = *reinterpret_cast<const uint32_t*>(a.bytes + base);
+            const int b0 = lo > base ? (int)(lo - base) : 0;
+            const int b1 = hi - base < 4 ? (int)(hi - base) : 4;
+            for (int b = b0; b < b1; ++b) {
+                const uint32_t c = (word >> (8 * b)) & 255u;
+                const uint32_t X0 = own0 ? (S0 & M[c * W + lane]) : 0u;
+                const uint32_t X1 = own1 ? (S1 & M[c * W + 64 + lane]) : 0u;
+                uint32_t N0 = 0, N1 = 0;
+                for (int half = 0; half < 2; ++half) {
+                    uint64_t nz = __ballot((half ? X1 : X0) != 0) & mine[half];
+                    while (nz) {
+                        const int wl = __builtin_ctzll(nz);
+                        nz &= nz - 1;
+                        uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)(half ? X1 : X0), wl);
+                        const int wordidx = wl + 64 * half;
+                        if (a.chunks) {
+                            const uint32_t* T = a.chunks + (size_t)wordidx * 4 * 256 * W;
+                            const uint32_t* r0 = T + (size_t)(0 * 256 + ((xw >> 0) & 255u)) * W;
+                            const uint32_t* r1 = T + (size_t)(1 * 256 + ((xw >> 8) & 255u)) * W;
+                            const uint32_t* r2 = T + (size_t)(2 * 256 + ((xw >> 16) & 255u)) * W;
+                            const uint32_t* r3 = T + (size_t)(3 * 256 + ((xw >> 24) & 255u)) * W;
+                            if (own0) N0 |= (r0[lane] | r1[lane]) | (r2[lane] | r3[lane]);
+                            if (own1) N1 |= (r0[lane + 64] | r1[lane + 64]) | (r2[lane + 64] | r3[lane + 64]);
+                            continue;
+                        }
+                        while (xw) {
+                            const int bit = __builtin_ctz(xw);
+                            xw &= xw - 1;
+                            const uint32_t* row = F + (size_t)(wordidx * 32 + bit) * W;
+                            if (own0) N0 |= row[lane];
+                            if (own1) N1 |= row[lane + 64];
+                        }
+                    }
+                }
+                // the partial sets meet: every wavefront leaves with the same S
+                part[parity][wave][lane] = N0;
+                part[parity][wave][lane + 64] = N1;
+                __syncthreads();
+                S0 = 0;
+                S1 = 0;
+#pragma unroll
+                for (int w = 0; w < WS; ++w) {
+                    S0 |= part[parity][w][lane];
+                    S1 |= part[parity][w][lane + 64];
+                }
+                parity ^= 1;
+            }
+            const bool live = __ballot((S0 | S1) != 0) != 0;
+            if (!live) { res = 0; break; }
+            if (a.suffix_any) {
+                const uint32_t sw = (uint32_t)__builtin_amdgcn_readlane((int)(aw < 64 ? S0 : S1), aw & 63);
+                if (sw & abit) { res = 1; break; }
+            }
+        }
+        if (res < 0) {
+            const uint32_t sw = (uint32_t)__builtin_amdgcn_readlane((int)(aw < 64 ? S0 : S1), aw & 63);
+            res = (sw & abit) ? 1 : 0;
+        }
+        if (threadIdx.x == 0) a.out[sid] = (uint8_t)res;
+        // the next string's first byte reuses the buffers: no wavefront may still read them
+        __syncthreads();
+    }
+}
+
 KArgs kargs(const LaunchArgs& a) {
     KArgs k;
     k.first = a.first;
@@ -340,7 +447,40 @@ int launch_lane(const LaunchArgs& a) {
     }
 }
 
+namespace {
+template <int WS>
+int launch_wave_split(const LaunchArgs& a, size_t lds) {
+    const int grid = (int)(a.n < (1 << 30) ? a.n : (1 << 30));
+    if (lds <= 150 * 1024) {
+        static bool attr_set = false;
+        if (!attr_set) {
+            hipFuncSetAttribute((const void*)k_wave_split<true, WS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                150 * 1024);
+            attr_set = true;
+        }
+        hipLaunchKernelGGL((k_wave_split<true, WS>), dim3(grid), dim3(64 * WS), lds, (hipStream_t)a.stream, kargs(a));
+    } else {
+        hipLaunchKernelGGL((k_wave_split<false, WS>), dim3(grid), dim3(64 * WS), 0, (hipStream_t)a.stream, kargs(a));
+    }
+    return (int)hipGetLastError();
+}
+}  // namespace
+
 int launch_wave(const LaunchArgs& a) {
+    const size_t lds_tables = 4 * (size_t)(256 + a.L) * a.W;
+    if (!a.rows_out && !a.first_pos && a.n > 0) {
+        // Few strings: several wavefronts per string keep the SIMDs busy.
+        // rx_launch.unroll picks wavefronts per string (1, 2 or 4; 0 = by count).
+        int ws = a.unroll;
+        if (ws == 0) {
+            int cus = 0;
+            if (hip_cu_count(&cus) || cus <= 0) cus = 256;
+            const int64_t simds = 4 * (int64_t)cus;
+            ws = a.n * 4 <= simds ? 4 : a.n * 2 <= simds ? 2 : 1;
+        }
+        if (ws == 4) return launch_wave_split<4>(a, lds_tables);
+        if (ws == 2) return launch_wave_split<2>(a, lds_tables);
+    }
     const int block = a.block > 0 ? a.block : 256;
     const int waves = block / 64;
     int64_t need = (a.n + waves - 1) / waves;

@@ -51,3 +51,21 @@ def test_tune_multi(dev, tmp_path):
     print("tuned multi:", info, flush=True)
     assert info["candidates"] == 27
     assert np.array_equal(rx.match_multi(ps, d, o, config=cfg).cpu().numpy(), want)
+
+
+def test_tune_multi_with_plane_form(dev, tmp_path):
+    """With the list prepared, the tuner also times the plane form; whatever wins gives the oracle's bits."""
+    from paper_1108_3126_amd import autotune, rx
+
+    progs = W.multi_programs(seed=6, count=3, lo=16, hi=200)
+    s = W.multi_lines(seed=6, n=6000, hi=900)
+    want = np.stack([oracle.match(p.ast, p.root, p.classes, True, s.data, s.offsets) for p in progs])
+    ps = [rx.compile(p.ast, p.root, p.classes, True).upload(dev) for p in progs]
+    rx.prepare_multi(ps)
+    d, o = torch.from_numpy(s.data).to(dev), torch.from_numpy(s.offsets).to(dev)
+    cfg, info = autotune.tune_multi(ps, d, o, budget_runs=40, cache_path=str(tmp_path / "t.json"), planes=True)
+    print("tuned multi with planes:", info, flush=True)
+    assert info["candidates"] == 28
+    assert np.array_equal(rx.match_multi(ps, d, o, config=cfg).cpu().numpy(), want)
+    cfg2, info2 = autotune.tune_multi(ps, d, o, cache_path=str(tmp_path / "t.json"), planes=True)
+    assert info2["cached"] and cfg2.form == cfg.form

@@ -78,6 +78,12 @@ def test_multi_16_programs_4m_lines(dev):
     out2 = rx.match_multi(ps, d, o, config=cfg)
     torch.cuda.synchronize()
     assert np.array_equal(out2.cpu().numpy(), got)
+    # the plane form (the benchmark's): every one of the 64M results equals the table form's
+    rx.prepare_multi(ps)
+    out3 = rx.match_multi(ps, d, o, config=rx.multi_config(form=rx.FORM_PLANES))
+    torch.cuda.synchronize()
+    bad = np.argwhere(out3.cpu().numpy() != got)
+    assert bad.size == 0, bad[:10]
     # a seeded subsample of 200,000 (line, program) pairs plus every line longer than 1 KiB against
     # every program, through the oracle
     rng = np.random.default_rng(7)
