@@ -82,6 +82,7 @@ def main():
     ap.add_argument("--workload", choices=["single", "small", "multi", "pathological", "long"], default="single",
                     help="single is the benchmark; the others measure the remaining configurations")
     ap.add_argument("--multi-lines", type=int, default=4_000_000)
+    ap.add_argument("--no-table", action="store_true", help="multi: time only the plane form (profiling runs)")
     ap.add_argument("--copy-bytes", type=int, default=1 << 28)
     args = ap.parse_args()
 
@@ -295,8 +296,11 @@ def run_multi(args, torch, dev):
     log(f"multi: {len(progs)} programs, {lines.n} lines, {lines.offsets[-1] / 1e6:.0f} MB in {time.time() - t0:.1f}s")
     ps = [rx.compile(p.ast, p.root, p.classes, True).upload(dev) for p in progs]
     d, o = torch.from_numpy(lines.data).to(dev), torch.from_numpy(lines.offsets).to(dev)
-    cfg, tinfo = autotune.tune_multi(ps, d, o, budget_runs=40, use_cache=False)
-    log(f"multi tuned: {tinfo}")
+    if args.no_table:
+        cfg, tinfo = None, None
+    else:
+        cfg, tinfo = autotune.tune_multi(ps, d, o, budget_runs=40, use_cache=False)
+        log(f"multi tuned: {tinfo}")
 
     def timed(config, reps=3):
         res = rx.match_multi(ps, d, o, config=config)
@@ -309,15 +313,15 @@ def run_multi(args, torch, dev):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps, res.cpu().numpy()
 
-    ms_table, got_table = timed(cfg)
+    ms_table, got_table = timed(cfg) if cfg is not None else (None, None)
     # plane form: each program's bit-sliced circuit over length-sorted slabs
     j0 = time.time()
     rx.prepare_multi(ps)
     jit_s = time.time() - j0
     pcfg = rx.multi_config(form=rx.FORM_PLANES, max_bytes=int(lines.offsets[-1]))
     ms_planes, got = timed(pcfg)
-    log(f"multi: table form {ms_table:.3f} ms, plane form {ms_planes:.3f} ms (circuits compiled in {jit_s:.1f} s)")
-    ok = bool(np.array_equal(got, got_table))
+    log(f"multi: table form {ms_table} ms, plane form {ms_planes:.3f} ms (circuits compiled in {jit_s:.1f} s)")
+    ok = got_table is None or bool(np.array_equal(got, got_table))
     rng = np.random.default_rng(7)
     for k, pr in enumerate(progs):
         idx = np.unique(rng.choice(lines.n, size=150, replace=False)).astype(np.int64)
@@ -328,9 +332,10 @@ def run_multi(args, torch, dev):
     return {"metric": "unique input GB/s, all programs per line", "workload": "multi: 16 programs x 4M lines",
             "form": "planes", "ms": round(ms, 3), "input_GBs": round(nbytes / (ms * 1e-3) / 1e9, 2),
             "byte_program_steps_per_s": round(nbytes * len(progs) / (ms * 1e-3), 0),
-            "table_form_ms": round(ms_table, 3), "speedup_vs_table": round(ms_table / ms, 2),
+            "table_form_ms": round(ms_table, 3) if ms_table else None,
+            "speedup_vs_table": round(ms_table / ms, 2) if ms_table else None,
             "accepted_per_program": got.sum(axis=1).tolist(), "table_config": tinfo,
-            "bit_exact_sample": ok, "planes_equal_table": bool(np.array_equal(got, got_table))}
+            "bit_exact_sample": ok, "planes_equal_table": None if got_table is None else bool(np.array_equal(got, got_table))}
 
 
 def run_pathological(args, torch, dev):
