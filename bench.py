@@ -302,13 +302,18 @@ def run_multi(args, torch, dev):
         cfg, tinfo = autotune.tune_multi(ps, d, o, budget_runs=40, use_cache=False)
         log(f"multi tuned: {tinfo}")
 
-    def timed(config, reps=3):
-        res = rx.match_multi(ps, d, o, config=config)
+    def timed(config, reps=3, dd=d, oo=o):
+        cfg_ = config if config is not None else rx.multi_config()
+        if cfg_.form == rx.FORM_PLANES:
+            cfg_ = rx.multi_config(form=rx.FORM_PLANES, max_bytes=dd.numel(), graph=cfg_.graph)
+        need = rx.lib().rx_match_multi_workspace(oo.numel() - 1, len(ps), rx.ctypes.byref(cfg_))
+        work = torch.empty(int(need) + 256, dtype=torch.uint8, device=dev)
+        res = rx.match_multi(ps, dd, oo, config=cfg_, work=work)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            rx.match_multi(ps, d, o, out=res, config=config)
+            rx.match_multi(ps, dd, oo, out=res, config=cfg_, work=work)
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps, res.cpu().numpy()
@@ -322,6 +327,21 @@ def run_multi(args, torch, dev):
     ms_planes, got = timed(pcfg)
     log(f"multi: table form {ms_table} ms, plane form {ms_planes:.3f} ms (circuits compiled in {jit_s:.1f} s)")
     ok = got_table is None or bool(np.array_equal(got, got_table))
+    # the same launches replayed from a captured graph, on the whole batch and on a small one (20,000
+    # lines), where the launch path is a larger share of a call
+    gcfg = rx.multi_config(form=rx.FORM_PLANES, max_bytes=int(lines.offsets[-1]), graph=True)
+    ms_graph, got_graph = timed(gcfg)
+    graph_ok = bool(np.array_equal(got_graph, got))
+    small_n = min(20000, lines.n)
+    ds, os_ = d[:int(lines.offsets[small_n])], o[:small_n + 1]
+    small = {"lines": small_n}
+    for name, c in (("planes", rx.multi_config(form=rx.FORM_PLANES)),
+                    ("planes_graph", rx.multi_config(form=rx.FORM_PLANES, graph=True)),
+                    ("table", rx.multi_config()), ("table_graph", rx.multi_config(graph=True))):
+        ms_s, got_s = timed(c, reps=50, dd=ds, oo=os_)
+        small[name + "_ms"] = round(ms_s, 4)
+        graph_ok = graph_ok and bool(np.array_equal(got_s, got[:, :small_n]))
+    log(f"multi: graph replay {ms_graph:.3f} ms; 20,000 lines: {small}; graph results equal: {graph_ok}")
     rng = np.random.default_rng(7)
     for k, pr in enumerate(progs):
         idx = np.unique(rng.choice(lines.n, size=150, replace=False)).astype(np.int64)
@@ -332,6 +352,7 @@ def run_multi(args, torch, dev):
     return {"metric": "unique input GB/s, all programs per line", "workload": "multi: 16 programs x 4M lines",
             "form": "planes", "ms": round(ms, 3), "input_GBs": round(nbytes / (ms * 1e-3) / 1e9, 2),
             "byte_program_steps_per_s": round(nbytes * len(progs) / (ms * 1e-3), 0),
+            "graph_ms": round(ms_graph, 3), "small_batch": small, "graph_equal_direct": graph_ok,
             "table_form_ms": round(ms_table, 3) if ms_table else None,
             "speedup_vs_table": round(ms_table / ms, 2) if ms_table else None,
             "accepted_per_program": got.sum(axis=1).tolist(), "table_config": tinfo,

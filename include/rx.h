@@ -434,7 +434,7 @@ typedef struct {
     int32_t block;      /* strings per work item = threads per workgroup: 64, 128 or 256 (default 256) */
     int32_t grid;       /* persistent workgroups (default 4 per compute unit) */
     int32_t form;       /* RX_FORM_TABLE (0, default) or RX_FORM_PLANES (see rx_match_multi) */
-    int32_t reserved;   /* 0 */
+    int32_t graph;      /* 1: replay the call's launches from a captured HIP graph (see rx_match_multi) */
     int64_t max_bytes;  /* RX_FORM_PLANES: at least the total bytes of all strings (e.g. the size of the
                            bytes buffer); sizes the workspace */
 } rx_multi_config;
@@ -474,10 +474,27 @@ int64_t rx_match_multi_workspace(int64_t n, int32_t n_progs, const rx_multi_conf
  * cfg->max_bytes must be at least the total length of the strings (with a
  * smaller bound the slabs are skipped and their results are unspecified; no
  * memory outside the workspace is touched).
+ *
+ * cfg->graph = 1 (either form): the call's launch sequence is recorded once
+ * by stream capture on a library stream of the current device, instantiated
+ * as a HIP graph and replayed on `stream`; a later call with the same programs
+ * and launch shape replays it, or updates it in place when only pointers and
+ * sizes changed (waiting on the host for that graph's previous replay first),
+ * else instantiates a new one.  Up to 8 graphs are kept per device, least
+ * recently used dropped first.  Instantiation allocates host memory; results
+ * equal those of the direct launches.  `stream` must not itself be capturing
+ * (under the caller's own capture use graph = 0: the direct launches are then
+ * what is captured).  Graph calls on one device are serialised by a lock on
+ * the host; calls sharing a workspace race on the device as direct calls do.
  */
 int rx_match_multi(const rx_program* const* progs, int32_t n_progs, const uint8_t* d_bytes,
                    const int64_t* d_offsets, int64_t n, uint8_t* d_out, void* d_work, size_t work_bytes,
                    const rx_multi_config* cfg, void* stream);
+
+/* Graph use of rx_match_multi since the process started (all devices):
+ * counts[0] replays as recorded, counts[1] in-place updates, counts[2]
+ * instantiations.  Errors: RX_EINVAL (NULL). */
+int rx_multi_graph_counts(int64_t counts[3]);
 
 /*
  * Autotuner for rx_match / rx_match_fixed: successive halving over the kernel

@@ -604,6 +604,28 @@ int match_multi_planes(const rx_program* const* progs, int32_t n_progs, const ui
     m.work = d_work;
     m.stream = stream;
     if (n == 0) return RX_OK;
+    if (cfg.graph) {
+        std::string topo = "planes", full;
+        graph_key(topo, n_progs);
+        for (int i = 0; i < n_progs; ++i) graph_key(topo, m.progs[i]->uid);
+        graph_key(topo, m.block_lines);
+        graph_key(topo, m.item_grid);
+        full = topo;
+        for (int i = 0; i < n_progs; ++i) graph_key(full, m.descs[i]);
+        graph_key(full, m.bytes);
+        graph_key(full, m.offsets);
+        graph_key(full, m.n);
+        graph_key(full, m.max_bytes);
+        graph_key(full, m.out);
+        graph_key(full, m.work);
+        const auto record = [&m](void* cs) {
+            PlaneMultiArgs r = m;
+            r.stream = cs;
+            return launch_planes_multi(r);
+        };
+        if (int e = graph_replay(topo, full, record, stream, nullptr)) return hip_fail(e, "plane-form graph");
+        return RX_OK;
+    }
     if (int e = launch_planes_multi(m)) return hip_fail(e, "plane-form launch");
     return RX_OK;
 }
@@ -623,6 +645,7 @@ int rx_match_multi(const rx_program* const* progs, int32_t n_progs, const uint8_
     MultiArgs m;
     if (int rc = multi_shape(cfg, m.edges, &m.n_edges, &m.block_lines, &m.grid)) return rc;
     if (cfg && cfg->form != RX_FORM_TABLE && cfg->form != RX_FORM_PLANES) return fail(RX_EINVAL, "unknown form");
+    if (cfg && cfg->graph != 0 && cfg->graph != 1) return fail(RX_EINVAL, "graph must be 0 or 1");
     if (cfg && cfg->form == RX_FORM_PLANES) return match_multi_planes(progs, n_progs, d_bytes, d_offsets, n, d_out,
                                                                      d_work, work_bytes, *cfg, m, stream);
     const int64_t need = multi_workspace_bytes(n, n_progs, m.n_edges + 1, m.block_lines);
@@ -650,7 +673,37 @@ int rx_match_multi(const rx_program* const* progs, int32_t n_progs, const uint8_
     m.work = d_work;
     m.stream = stream;
     if (n == 0) return RX_OK;
+    if (cfg && cfg->graph) {
+        std::string topo = "table", full;
+        graph_key(topo, n_progs);
+        graph_key(topo, m.n_edges);
+        graph_key(topo, m.edges);
+        graph_key(topo, m.block_lines);
+        graph_key(topo, m.grid);
+        full = topo;
+        for (int i = 0; i < n_progs; ++i) graph_key(full, m.progs[i]);
+        graph_key(full, m.bytes);
+        graph_key(full, m.offsets);
+        graph_key(full, m.n);
+        graph_key(full, m.out);
+        graph_key(full, m.work);
+        const auto record = [&m](void* cs) {
+            MultiArgs r = m;
+            r.stream = cs;
+            return launch_multi(r);
+        };
+        if (int e = graph_replay(topo, full, record, stream, nullptr)) return hip_fail(e, "batched graph");
+        return RX_OK;
+    }
     if (int e = launch_multi(m)) return hip_fail(e, "batched launch");
+    return RX_OK;
+    RX_GUARD_END
+}
+
+int rx_multi_graph_counts(int64_t counts[3]) {
+    RX_GUARD_BEGIN
+    if (!counts) return fail(RX_EINVAL, "NULL counts");
+    graph_counts(counts);
     return RX_OK;
     RX_GUARD_END
 }

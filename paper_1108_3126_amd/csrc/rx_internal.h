@@ -4,6 +4,7 @@
 
 #include <array>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -140,6 +141,18 @@ int launch_planes_multi(const PlaneMultiArgs& m);
 int launch_multi(const MultiArgs& m);
 int launch_items(const ItemsArgs& m);
 
+// graph replay of a launch sequence (rx_graph.cpp): `record` issues the
+// sequence on the stream it is given (a capture stream); calls with equal
+// `full` keys replay the instantiated graph, calls with another `full` but the
+// same `topo` update it in place.  *how (may be NULL): 0 replayed, 1 updated,
+// 2 instantiated.  Returns a HIP error code or the recorder's own.
+int graph_replay(const std::string& topo, const std::string& full, const std::function<int(void*)>& record,
+                 void* stream, int* how);
+void graph_counts(int64_t out[3]);
+void graph_key_add(std::string& key, const void* p, size_t n);
+template <class T>
+void graph_key(std::string& key, const T& v) { graph_key_add(key, &v, sizeof(v)); }
+
 // autotuner (rx_autotune.cpp)
 int autotune_single(const Program* P, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t length, int64_t n,
                     uint8_t* d_out, int budget_runs, rx_launch* best, double* best_ms, int* n_cands, void* stream);
@@ -204,9 +217,11 @@ std::string jit_planes_source(const Program& P, int* n_state);   // the list of 
 // Compiles and loads (once per device and list) the module of `progs`.
 int jit_prepare_planes(const Program* const* progs, int n, const char* arch, int* spill_bytes);
 bool jit_planes_prepared(const Program* const* progs, int n);
-// One wavefront per (program, slab); returns -1 when the list was not prepared.
+// One wavefront per (program, slab) for the slabs of rank r_lo <= r < r_hi
+// (rank 0 = the longest); returns -1 when the list was not prepared.
 int launch_planes_circuits(const Program* const* progs, int n, const uint32_t* planes, const int64_t* slab_tick,
-                           const int64_t* info, uint32_t* res, int64_t max_slabs, void* stream);
+                           const int64_t* info, uint32_t* res, int64_t max_slabs, int64_t r_lo, int64_t r_hi,
+                           void* stream);
 // Static check of a register-staged kernel in a code object (rx_isa_guard.cpp):
 // *violations = instructions not written by the kernel itself that name an
 // accumulation register.  Returns 0 when the check ran, < 0 when it could not.

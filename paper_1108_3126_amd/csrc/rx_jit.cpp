@@ -915,20 +915,21 @@ __device__ __forceinline__ void rx_run_slab(const u32* __restrict__ planes, cons
     res[lane] = accf;   // one coalesced word per lane
 }
 
-// One wavefront per (program, slab).  Workgroup b runs on XCD b mod 8; its
-// slab rank (0 = longest) is 8 * ((b / 8) / n_progs) + b mod 8 and its
-// program (b / 8) mod n_progs.  info[0] = strings in slabs; the results of
-// program p and slab s go to res[(p * max_slabs + s) * 64 .. + 64).
+// One wavefront per (program, slab) for the slabs of rank r_lo <= r < r_hi
+// (rank 0 = the longest slab).  Workgroup b runs on XCD b mod 8; its slab
+// rank is r_lo + 8 * ((b / 8) / n_progs) + b mod 8 and its program (b / 8)
+// mod n_progs.  info[0] = strings in slabs; the results of program p and
+// slab s go to res[(p * max_slabs + s) * 64 .. + 64).
 extern "C" __global__ __launch_bounds__(64) void rx_planes_multi(const u32* __restrict__ planes,
         const long long* __restrict__ slab_tick, const long long* __restrict__ info, u32* __restrict__ res,
-        long long max_slabs) {
+        long long max_slabs, long long r_lo, long long r_hi) {
     const long long b = blockIdx.x;
     const long long k = b >> 3;
     const int p = (int)(k % RX_NPROGS);
-    const long long r = (k / RX_NPROGS) * 8 + (b & 7);
+    const long long r = r_lo + (k / RX_NPROGS) * 8 + (b & 7);
     const long long n_sliced = info[0];
     const long long S = (n_sliced + 2047) / 2048;
-    if (r >= S) return;
+    if (r >= S || r >= r_hi) return;
     // the longest slabs set the kernel's length: their wavefronts issue first on their SIMDs
     if (r < 16) __builtin_amdgcn_s_setprio(3);
     rx_dispatch(p, planes, slab_tick, S - 1 - r, res + (p * max_slabs + (S - 1 - r)) * 64);
@@ -1144,7 +1145,8 @@ bool jit_planes_prepared(const Program* const* progs, int n) {
 }
 
 int launch_planes_circuits(const Program* const* progs, int n, const uint32_t* planes, const int64_t* slab_tick,
-                           const int64_t* info, uint32_t* res, int64_t max_slabs, void* stream) {
+                           const int64_t* info, uint32_t* res, int64_t max_slabs, int64_t r_lo, int64_t r_hi,
+                           void* stream) {
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return (int)hipErrorInvalidDevice;
     PlaneModule* K = nullptr;
@@ -1154,15 +1156,16 @@ int launch_planes_circuits(const Program* const* progs, int n, const uint32_t* p
         if (it != g_plane_mods.end()) K = it->second;
     }
     if (!K) return -1;   // not prepared
-    if (max_slabs <= 0) return 0;
-    const long long per = (max_slabs + 7) / 8;
+    const int64_t hi = r_hi < max_slabs ? r_hi : max_slabs;
+    if (hi <= r_lo) return 0;
+    const long long per = (hi - r_lo + 7) / 8;
     const unsigned grid = (unsigned)(8 * per * n);
     const void* a0 = planes;
     const void* a1 = slab_tick;
     const void* a2 = info;
     void* a3 = res;
-    long long a4 = max_slabs;
-    void* args[] = {&a0, &a1, &a2, &a3, &a4};
+    long long a4 = max_slabs, a5 = r_lo, a6 = hi;
+    void* args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6};
     return (int)hipModuleLaunchKernel(K->fn, grid, 1, 1, 64, 1, 1, 0, (hipStream_t)stream, args, nullptr);
 }
 

@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
 
 #include "rx_internal.h"
 #include "rx_planes.h"
@@ -293,6 +295,7 @@ struct SortArgs {
 };
 
 constexpr int kGroupTicks = 64;   // plane-kernel work unit: 256 positions of one slab
+constexpr int64_t kLongSlabs = 16;   // slabs whose circuits start first, on their own stream
 
 __device__ __forceinline__ int sort_bin(int64_t len) { return len < kSortBins - 1 ? (int)len : kSortBins - 1; }
 
@@ -428,6 +431,7 @@ struct PlanesArgs {
     const int64_t* slab_tick;
     const int64_t* slab_chunk;
     uint32_t* planes;
+    int64_t r_lo, r_hi;   // the slabs of rank r_lo <= r < r_hi (rank 0 = the longest)
 };
 
 // Gathers and transposes: one workgroup per group of kGroupTicks ticks of a
@@ -436,16 +440,18 @@ struct PlanesArgs {
 // the slab's strings at about the same time.  Lane l reads a 16-byte window
 // of each of its 32 strings and writes four ticks of plane words (1 KiB per
 // group of four words, coalesced).  A slab of n ticks takes n / kGroupTicks
-// workgroups, so the longest slabs do not serialise the kernel.
+// workgroups, so the longest slabs do not serialise the kernel.  Only the
+// slabs of rank r_lo .. r_hi - 1 (rank 0 = the longest, slab S - 1).
 __global__ __launch_bounds__(256, 2) void k_planes(PlanesArgs a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t n_sliced = a.info[0];
     const int64_t S = (n_sliced + kSlabStrings - 1) / kSlabStrings;
-    const int64_t groups = a.info[2];
-    const int64_t u = groups - 1 - (int64_t)blockIdx.x;   // the last groups belong to the longest slabs
-    if (u < 0) return;
+    const int64_t s_first = S - a.r_hi > 0 ? S - a.r_hi : 0, s_end = S - a.r_lo > 0 ? S - a.r_lo : 0;
+    if (s_first >= s_end) return;
+    const int64_t u = a.slab_chunk[s_end] - 1 - (int64_t)blockIdx.x;   // the last groups belong to the longest slabs
+    if (u < a.slab_chunk[s_first]) return;
     // the slab holding group u: the last s with slab_chunk[s] <= u
-    int64_t lo = 0, hi = S - 1;
+    int64_t lo = s_first, hi = s_end - 1;
     while (lo < hi) {
         const int64_t mid = (lo + hi + 1) >> 1;
         if (a.slab_chunk[mid] <= u) lo = mid;
@@ -551,6 +557,44 @@ __global__ void k_over_fill(OverArgs a) {
 
 }  // namespace
 
+namespace {
+// A second stream per device for the longest slabs' circuits, with the
+// events that fork it from and join it to the caller's stream; the lock keeps
+// each call's record/wait pairs together.  A stream under capture gets a
+// side stream of its own (it stays in the capture until the capture ends).
+struct SideStream {
+    std::mutex mu;
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+int side_stream(hipStream_t st, SideStream** out) {
+    static std::mutex g_mu;
+    static std::map<std::pair<int, int>, SideStream*> g_side;
+    int dev = -1;
+    if (hipError_t e = hipGetDevice(&dev)) return (int)e;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipError_t e = hipStreamIsCapturing(st, &cap)) return (int)e;
+    std::lock_guard<std::mutex> lk(g_mu);
+    SideStream*& S = g_side[{dev, cap == hipStreamCaptureStatusNone ? 0 : 1}];
+    if (!S) {
+        SideStream* x = new SideStream;
+        hipError_t e = hipStreamCreateWithFlags(&x->stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&x->fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&x->join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (x->fork) (void)hipEventDestroy(x->fork);
+            if (x->stream) (void)hipStreamDestroy(x->stream);
+            delete x;
+            return (int)e;
+        }
+        S = x;
+    }
+    *out = S;
+    return 0;
+}
+}  // namespace
+
 int64_t plane_max_slabs(int64_t n) { return (n + kSlabStrings - 1) / kSlabStrings; }
 
 int64_t plane_tick_cap(int64_t n, int64_t max_bytes) {
@@ -600,6 +644,9 @@ int launch_planes_multi(const PlaneMultiArgs& m) {
     uint32_t* planes = reinterpret_cast<uint32_t*>(w);
     a.max_slabs = S;
     a.tick_cap = plane_tick_cap(m.n, m.max_bytes);
+    SideStream* side = nullptr;
+    if (int e = side_stream(st, &side)) return e;
+    std::lock_guard<std::mutex> lk(side->mu);
     const int gs = (int)((m.n + 255) / 256 < 1024 ? (m.n + 255) / 256 : 1024);
     hipLaunchKernelGGL(k_sort_clear, dim3((kSortBins + 255) / 256), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_sort_count, dim3(gs > 0 ? gs : 1), dim3(256), 0, st, a);
@@ -614,10 +661,27 @@ int launch_planes_multi(const PlaneMultiArgs& m) {
     pa.slab_tick = a.slab_tick;
     pa.slab_chunk = a.slab_chunk;
     pa.planes = planes;
-    hipLaunchKernelGGL(k_planes, dim3((unsigned)(a.tick_cap / kGroupTicks + S + 1)), dim3(256), 0, st, pa);
+    // The longest slabs first, their circuits on a second stream: a slab's
+    // circuit runs one position after another, so the few longest set the
+    // length of the call; the planes and circuits of every other slab run
+    // beside them.
+    const int64_t R = kLongSlabs < S ? kLongSlabs : S;
+    pa.r_lo = 0;
+    pa.r_hi = R;
+    hipLaunchKernelGGL(k_planes, dim3((unsigned)(R * (kSortBins / (4 * kGroupTicks) + 1))), dim3(256), 0, st, pa);
     if (hipError_t e = hipGetLastError()) return (int)e;
-    // every (program, slab) pair in one launch, then the results in string order
-    if (int e = launch_planes_circuits(m.progs, m.n_progs, planes, a.slab_tick, a.info, res, S, m.stream)) return e;
+    if (hipError_t e = hipEventRecord(side->fork, st)) return (int)e;
+    if (hipError_t e = hipStreamWaitEvent(side->stream, side->fork, 0)) return (int)e;
+    if (int e = launch_planes_circuits(m.progs, m.n_progs, planes, a.slab_tick, a.info, res, S, 0, R, side->stream))
+        return e;
+    if (hipError_t e = hipEventRecord(side->join, side->stream)) return (int)e;
+    pa.r_lo = R;
+    pa.r_hi = S;
+    if (S > R) hipLaunchKernelGGL(k_planes, dim3((unsigned)(a.tick_cap / kGroupTicks + S + 1)), dim3(256), 0, st, pa);
+    if (hipError_t e = hipGetLastError()) return (int)e;
+    if (int e = launch_planes_circuits(m.progs, m.n_progs, planes, a.slab_tick, a.info, res, S, R, S, m.stream))
+        return e;
+    if (hipError_t e = hipStreamWaitEvent(st, side->join, 0)) return (int)e;
     GatherArgs ga;
     ga.rank = a.rank;
     ga.info = a.info;

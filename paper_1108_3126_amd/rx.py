@@ -48,21 +48,21 @@ class rx_node(ctypes.Structure):
 
 class rx_multi_config(ctypes.Structure):
     _fields_ = [("n_edges", ctypes.c_int32), ("edges", ctypes.c_int32 * 15), ("block", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("form", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("form", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("max_bytes", ctypes.c_int64)]
 
 
 FORM_TABLE, FORM_PLANES = 0, 1
 
 
-def multi_config(edges=None, block=0, grid=0, form=FORM_TABLE, max_bytes=0) -> "rx_multi_config":
+def multi_config(edges=None, block=0, grid=0, form=FORM_TABLE, max_bytes=0, graph=False) -> "rx_multi_config":
     c = rx_multi_config()
     if edges:
         c.n_edges = len(edges)
         for i, e in enumerate(edges):
             c.edges[i] = int(e)
     c.block, c.grid = int(block), int(grid)
-    c.form, c.max_bytes = int(form), int(max_bytes)
+    c.form, c.max_bytes, c.graph = int(form), int(max_bytes), int(bool(graph))
     return c
 
 
@@ -120,6 +120,7 @@ SIGNATURES = {
     "rx_parse": (ctypes.c_int, [ctypes.c_char_p, _SZ, _VP, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _VP, _I32,
                                 ctypes.POINTER(_I32)]),
     "rx_match_multi_workspace": (ctypes.c_int64, [_I64, _I32, ctypes.POINTER(rx_multi_config)]),
+    "rx_multi_graph_counts": (ctypes.c_int, [ctypes.POINTER(_I64)]),
     "rx_match_multi": (ctypes.c_int, [ctypes.POINTER(_VP), _I32, _VP, _VP, _I64, _VP, _VP, _SZ,
                                       ctypes.POINTER(rx_multi_config), _VP]),
     "rx_autotune": (ctypes.c_int, [_VP, _VP, _VP, _I64, _I64, _VP, _I32, ctypes.POINTER(rx_launch),
@@ -544,7 +545,7 @@ def match_multi(progs, data, offsets, out=None, config=None, work=None, stream=N
     cfg = config if config is not None else rx_multi_config()
     if cfg.form == FORM_PLANES and cfg.max_bytes < data.numel():
         # the plane workspace is sized by a bound on the total string bytes: the buffer's size
-        cfg = multi_config(list(cfg.edges)[:cfg.n_edges], cfg.block, cfg.grid, FORM_PLANES, data.numel())
+        cfg = multi_config(list(cfg.edges)[:cfg.n_edges], cfg.block, cfg.grid, FORM_PLANES, data.numel(), cfg.graph)
     need = lib().rx_match_multi_workspace(n, P, ctypes.byref(cfg))
     if need < 0:
         _check(int(need))
@@ -560,6 +561,13 @@ def match_multi(progs, data, offsets, out=None, config=None, work=None, stream=N
                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(wptr), int(need),
                                 ctypes.byref(cfg), _stream_handle(stream)))
     return out
+
+
+def multi_graph_counts():
+    """(replays, in-place updates, instantiations) of rx_match_multi's graphs so far."""
+    c = (ctypes.c_int64 * 3)()
+    _check(lib().rx_multi_graph_counts(c))
+    return tuple(int(x) for x in c)
 
 
 def stream_copy(dst, src, nbytes=None, stream=None):

@@ -153,3 +153,51 @@ def test_planes_repeat_calls_share_workspace(dev, multi_case):
     o2 = torch.from_numpy(s.offsets[:1001].copy()).to(dev)
     b = rx.match_multi(ps, d, o2, config=cfg, work=work).cpu().numpy()
     assert np.array_equal(a, want[:3]) and np.array_equal(b, want[:3, :1000])
+
+
+# -- captured graphs: the same launches replayed ---------------------------------
+@pytest.mark.parametrize("form", ["table", "planes"])
+def test_graph_replay_equals_direct(dev, multi_case, form):
+    """cfg.graph = 1: the first call instantiates, an identical call replays, a call on other buffers and
+    fewer strings updates (or re-instantiates) the graph; every replay equals the oracle, with eager work
+    and synchronisation between the replays."""
+    from paper_1108_3126_amd import rx
+
+    progs, s, want = multi_case
+    ps = [rx.compile(p.ast, p.root, p.classes, p.search).upload(dev) for p in progs[:4]]
+    fm = rx.FORM_PLANES if form == "planes" else rx.FORM_TABLE
+    if form == "planes":
+        rx.prepare_multi(ps)
+    d, o = torch.from_numpy(s.data).to(dev), torch.from_numpy(s.offsets).to(dev)
+    cfg = rx.multi_config(form=fm, max_bytes=d.numel(), graph=True)
+    direct = rx.multi_config(form=fm, max_bytes=d.numel())
+    need = rx.lib().rx_match_multi_workspace(s.n, 4, rx.ctypes.byref(cfg))
+    work = torch.empty(int(need) + 256, dtype=torch.uint8, device=dev)
+    out = torch.empty((4, s.n), dtype=torch.uint8, device=dev)
+    c0 = rx.multi_graph_counts()
+    for rep in range(3):
+        out.fill_(7)
+        rx.match_multi(ps, d, o, out=out, config=cfg, work=work)
+        torch.cuda.synchronize()
+        print(f"graph {form} replay {rep}: counts {rx.multi_graph_counts()}", flush=True)
+        assert np.array_equal(out.cpu().numpy(), want[:4]), rep
+        # eager work between replays: a direct call on the same workspace, then a torch op
+        assert np.array_equal(rx.match_multi(ps, d, o, config=direct, work=work).cpu().numpy(), want[:4])
+        torch.cuda.synchronize()
+    c1 = rx.multi_graph_counts()
+    assert c1[2] - c0[2] == 1 and c1[0] - c0[0] == 2, (c0, c1)
+    # other buffers, fewer strings: updated in place or instantiated again
+    o2 = torch.from_numpy(s.offsets[:1201].copy()).to(dev)
+    out2 = torch.empty((4, 1200), dtype=torch.uint8, device=dev)
+    for rep in range(2):
+        out2.fill_(7)
+        rx.match_multi(ps, d, o2, out=out2, config=cfg, work=work)
+        torch.cuda.synchronize()
+        assert np.array_equal(out2.cpu().numpy(), want[:4, :1200]), rep
+    c2 = rx.multi_graph_counts()
+    assert (c2[1] - c1[1]) + (c2[2] - c1[2]) == 1 and c2[0] - c1[0] == 1, (c1, c2)
+    # and back to the first call's arguments
+    out.fill_(7)
+    rx.match_multi(ps, d, o, out=out, config=cfg, work=work)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want[:4])
