@@ -859,10 +859,10 @@ extern "C" __global__ __launch_bounds__(64, 1) void rx_sliced_fixed_pf(const uns
 // after the string's last byte (the start value for the empty string).
 //
 // One module holds the circuits of every program of a call (one struct per
-// program), so a single launch runs every (program, slab) pair: the longest
-// slabs of all programs start first, and the programs of one slab run side by
-// side on one XCD (workgroups go to the XCDs in turn, blockIdx mod 8), where
-// they share that slab's planes in the XCD's L2.
+// program), so one launch runs every (program, slab) pair of a range of
+// slabs: the longest slabs of all programs start first, and the programs of
+// one slab run side by side on one XCD (workgroups go to the XCDs in turn,
+// blockIdx mod 8), where they share that slab's planes in the XCD's L2.
 const char* kPlanesTickSource = R"RX(
 template <class PR>
 __device__ __forceinline__ void rx_planes_tick(u32 (&s)[PR::NS], u32& acc, u32& accf, const u32 (&w)[36]) {
@@ -884,33 +884,38 @@ typedef unsigned int rx_pv4 __attribute__((ext_vector_type(4)));
 template <class PR>
 __device__ __forceinline__ void rx_run_slab(const u32* __restrict__ planes, const long long* __restrict__ slab_tick,
                                             long long s, u32* __restrict__ res) {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const long long t0 = slab_tick[s], T = slab_tick[s + 1] - t0;
     const rx_pv4* p = reinterpret_cast<const rx_pv4*>(planes) + t0 * (9 * 64) + lane;
     u32 st[PR::NS];
     u32 acc;
     PR::init(st, acc);
     u32 accf = acc;
+    // The registers of a position's planes are refilled with the next tick's
+    // as soon as that position is done, so every load has a whole tick to
+    // arrive and no second set of registers is needed.  The first tick's
+    // values get a use of their own before the loop: the compiler then keeps
+    // the loop's loads where they are instead of merging each with the first
+    // tick's into one load at the top of the loop, next to its first use.
     rx_pv4 cur[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) cur[q] = T > 0 ? p[q * 64] : rx_pv4{0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int q = 0; q < 9; ++q) asm volatile("" ::"v"(cur[q]));
     for (long long t = 0; t < T; ++t) {
-        // the next tick streams in while this one runs
         const rx_pv4* pn = p + (t + 1 < T ? t + 1 : t) * (9 * 64);
-        rx_pv4 nxt[9];
+        const u32 v[4] = {cur[8].x, cur[8].y, cur[8].z, cur[8].w};
+        cur[8] = pn[8 * 64];
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) nxt[q] = pn[q * 64];
-        u32 w[36];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            w[4 * q] = cur[q].x;
-            w[4 * q + 1] = cur[q].y;
-            w[4 * q + 2] = cur[q].z;
-            w[4 * q + 3] = cur[q].w;
+        for (int i = 0; i < 4; ++i) {
+            PR::step(st, acc, cur[2 * i].x, cur[2 * i].y, cur[2 * i].z, cur[2 * i].w, cur[2 * i + 1].x,
+                     cur[2 * i + 1].y, cur[2 * i + 1].z, cur[2 * i + 1].w);
+            accf = (acc & v[i]) | (accf & ~v[i]);
+            cur[2 * i] = pn[(2 * i) * 64];
+            cur[2 * i + 1] = pn[(2 * i + 1) * 64];
+            __builtin_amdgcn_sched_barrier(0);
         }
-        rx_planes_tick<PR>(st, acc, accf, w);
-#pragma unroll
-        for (int q = 0; q < 9; ++q) cur[q] = nxt[q];
     }
     res[lane] = accf;   // one coalesced word per lane
 }
