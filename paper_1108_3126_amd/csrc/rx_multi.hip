@@ -440,15 +440,19 @@ struct PlanesArgs {
 // the slab's strings at about the same time.  Lane l reads a 16-byte window
 // of each of its 32 strings and writes four ticks of plane words (1 KiB per
 // group of four words, coalesced).  A slab of n ticks takes n / kGroupTicks
-// workgroups, so the longest slabs do not serialise the kernel.  Only the
-// slabs of rank r_lo .. r_hi - 1 (rank 0 = the longest, slab S - 1).
+// workgroups, so the longest slabs do not serialise the kernel; with SPLIT,
+// the four rounds of a group (chunks 4 i .. 4 i + 3) go to four workgroups,
+// for the few longest slabs whose planes are wanted first.  Only the slabs of
+// rank r_lo .. r_hi - 1 (rank 0 = the longest, slab S - 1).
+template <bool SPLIT>
 __global__ __launch_bounds__(256, 2) void k_planes(PlanesArgs a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t n_sliced = a.info[0];
     const int64_t S = (n_sliced + kSlabStrings - 1) / kSlabStrings;
     const int64_t s_first = S - a.r_hi > 0 ? S - a.r_hi : 0, s_end = S - a.r_lo > 0 ? S - a.r_lo : 0;
     if (s_first >= s_end) return;
-    const int64_t u = a.slab_chunk[s_end] - 1 - (int64_t)blockIdx.x;   // the last groups belong to the longest slabs
+    const int64_t unit = SPLIT ? (int64_t)(blockIdx.x >> 2) : (int64_t)blockIdx.x;
+    const int64_t u = a.slab_chunk[s_end] - 1 - unit;   // the last groups belong to the longest slabs
     if (u < a.slab_chunk[s_first]) return;
     // the slab holding group u: the last s with slab_chunk[s] <= u
     int64_t lo = s_first, hi = s_end - 1;
@@ -460,6 +464,10 @@ __global__ __launch_bounds__(256, 2) void k_planes(PlanesArgs a) {
     const int64_t s = lo;
     const int64_t g = u - a.slab_chunk[s];
     const int64_t t_base = a.slab_tick[s], T = a.slab_tick[s + 1] - t_base;
+    const int64_t c_end = (g + 1) * (kGroupTicks / 4) < (T + 3) / 4 ? (g + 1) * (kGroupTicks / 4) : (T + 3) / 4;
+    const int64_t c_begin = g * (kGroupTicks / 4) + (SPLIT ? 4 * (int64_t)(blockIdx.x & 3) : 0);
+    const int64_t c_stop = SPLIT ? (c_begin + 4 < c_end ? c_begin + 4 : c_end) : c_end;
+    if (c_begin >= c_stop) return;
     const int64_t first = a.sorted[s * kSlabStrings];
     const int64_t minlen = a.offsets[first + 1] - a.offsets[first];
     // where the slab's strings are, once per workgroup (the four wavefronts share them)
@@ -477,8 +485,7 @@ __global__ __launch_bounds__(256, 2) void k_planes(PlanesArgs a) {
         s_len[k] = (int32_t)n;   // slab strings are shorter than kSortBins
     }
     __syncthreads();
-    const int64_t c_end = (g + 1) * (kGroupTicks / 4) < (T + 3) / 4 ? (g + 1) * (kGroupTicks / 4) : (T + 3) / 4;
-    for (int64_t c = g * (kGroupTicks / 4) + wave; c < c_end; c += 4) {
+    for (int64_t c = c_begin + wave; c < c_stop; c += 4) {
         uint32_t win[32][4];
         int32_t len[32];
 #pragma unroll
@@ -502,26 +509,51 @@ __global__ __launch_bounds__(256, 2) void k_planes(PlanesArgs a) {
 // Results back in the strings' own order: string i went to sorted position
 // rank[i] (slab r / 2048, entry r % 2048 = 64 j + l: bit j of lane l's word).
 // One thread per string and program, consecutive threads on consecutive
-// strings, so the result bytes are written in order; strings too long for a
-// slab are left to the table-form kernel.
+// strings, so the result bytes are written in order.  The strings of the
+// long_slabs longest slabs are left to k_gather_long (their circuits run on
+// the other stream and may still be running), those too long for a slab to
+// the table-form kernel.
 struct GatherArgs {
     const int32_t* rank;
+    const int32_t* sorted;
     const int64_t* info;
     const uint32_t* res;
-    int64_t max_slabs, n;
+    int64_t max_slabs, n, long_slabs;
     uint8_t* out;
 };
 
+// the first sorted position of the long slabs
+__device__ __forceinline__ int64_t long_cut(const GatherArgs& a, int64_t n_sliced) {
+    const int64_t S = (n_sliced + kSlabStrings - 1) / kSlabStrings;
+    return S > a.long_slabs ? (S - a.long_slabs) * kSlabStrings : 0;
+}
+
 __global__ __launch_bounds__(256) void k_gather_out(GatherArgs a) {
     const int64_t n_sliced = a.info[0];
+    const int64_t cut = long_cut(a, n_sliced);
     const int64_t p = blockIdx.y;
     const uint32_t* res = a.res + p * a.max_slabs * 64;
     uint8_t* out = a.out + p * a.n;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = a.rank[i];
-        if (r >= n_sliced) continue;
+        if (r >= cut) continue;
         const int64_t k = r & (kSlabStrings - 1);
         out[i] = (uint8_t)((res[(r >> 11) * 64 + (k & 63)] >> (k >> 6)) & 1u);
+    }
+}
+
+// The long slabs' results: one thread per sorted position e of those slabs
+// and program, written to string sorted[e].
+__global__ __launch_bounds__(256) void k_gather_long(GatherArgs a) {
+    const int64_t n_sliced = a.info[0];
+    const int64_t cut = long_cut(a, n_sliced);
+    const int64_t p = blockIdx.y;
+    const uint32_t* res = a.res + p * a.max_slabs * 64;
+    uint8_t* out = a.out + p * a.n;
+    for (int64_t e = cut + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_sliced;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e & (kSlabStrings - 1);
+        out[a.sorted[e]] = (uint8_t)((res[(e >> 11) * 64 + (k & 63)] >> (k >> 6)) & 1u);
     }
 }
 
@@ -668,7 +700,8 @@ int launch_planes_multi(const PlaneMultiArgs& m) {
     const int64_t R = kLongSlabs < S ? kLongSlabs : S;
     pa.r_lo = 0;
     pa.r_hi = R;
-    hipLaunchKernelGGL(k_planes, dim3((unsigned)(R * (kSortBins / (4 * kGroupTicks) + 1))), dim3(256), 0, st, pa);
+    hipLaunchKernelGGL(k_planes<true>, dim3((unsigned)(4 * R * (kSortBins / (4 * kGroupTicks) + 1))), dim3(256), 0, st,
+                       pa);
     if (hipError_t e = hipGetLastError()) return (int)e;
     if (hipError_t e = hipEventRecord(side->fork, st)) return (int)e;
     if (hipError_t e = hipStreamWaitEvent(side->stream, side->fork, 0)) return (int)e;
@@ -677,20 +710,26 @@ int launch_planes_multi(const PlaneMultiArgs& m) {
     if (hipError_t e = hipEventRecord(side->join, side->stream)) return (int)e;
     pa.r_lo = R;
     pa.r_hi = S;
-    if (S > R) hipLaunchKernelGGL(k_planes, dim3((unsigned)(a.tick_cap / kGroupTicks + S + 1)), dim3(256), 0, st, pa);
+    if (S > R)
+        hipLaunchKernelGGL(k_planes<false>, dim3((unsigned)(a.tick_cap / kGroupTicks + S + 1)), dim3(256), 0, st, pa);
     if (hipError_t e = hipGetLastError()) return (int)e;
     if (int e = launch_planes_circuits(m.progs, m.n_progs, planes, a.slab_tick, a.info, res, S, R, S, m.stream))
         return e;
-    if (hipError_t e = hipStreamWaitEvent(st, side->join, 0)) return (int)e;
     GatherArgs ga;
     ga.rank = a.rank;
+    ga.sorted = a.sorted;
     ga.info = a.info;
     ga.res = res;
     ga.max_slabs = S;
     ga.n = m.n;
+    ga.long_slabs = R;
     ga.out = m.out;
     const unsigned gx = (unsigned)((m.n + 255) / 256 < 2048 ? (m.n + 255) / 256 : 2048);
     hipLaunchKernelGGL(k_gather_out, dim3(gx, (unsigned)m.n_progs), dim3(256), 0, st, ga);
+    // then the long slabs, once their circuits are done
+    if (hipError_t e = hipStreamWaitEvent(st, side->join, 0)) return (int)e;
+    hipLaunchKernelGGL(k_gather_long, dim3((unsigned)((R * kSlabStrings + 255) / 256), (unsigned)m.n_progs), dim3(256), 0,
+                       st, ga);
     // strings too long for a slab: table form, every program
     OverArgs o;
     o.info = a.info;
