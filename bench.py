@@ -201,7 +201,8 @@ def main():
     log(f"kernel id {kid}; recorded traffic per launch: {traffic}")
     variant_name = {0: "auto", 1: "lane", 2: "wave", 3: "sliced"}[args.variant]
     if args.variant == 0:
-        variant_name = "sliced" if (args.layout == "fixed" and not args.no_jit) else "lane"
+        # offsets: a layout check on the device sends equal-length consecutive strings to the sliced kernel
+        variant_name = ("sliced" if args.layout == "fixed" else "layout check + sliced") if not args.no_jit else "lane"
     rec = {
         "metric": "input GB/s scanned (bit-exact)",
         "value": round(value, 3),

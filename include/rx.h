@@ -194,7 +194,16 @@ int rx_program_upload(rx_program* prog, void* d_buf, size_t cap, void* stream);
  * RX_SEARCH), else 0.  Runs asynchronously on `stream`; allocates nothing.
  * n == 0 is a no-op.  The kernel variant is chosen from the program's size:
  * one lane per string for sets of up to 16 words, one wavefront per string
- * above that.  Errors: RX_EINVAL, RX_ENOTUPLOADED, RX_EHIP.
+ * above that.  When the program's bit-sliced circuit is compiled
+ * (rx_program_jit) and n >= 16384, a check on the device decides whether the
+ * strings are equal-length and consecutive (offsets[i] = offsets[0] + i * len,
+ * len a multiple of 16 up to 2^26, d_bytes + offsets[0] 16-byte aligned); if
+ * so the bit-sliced kernel of rx_match_fixed matches them and the table-form
+ * launch does nothing, else the reverse (both are queued; the bits are the
+ * same either way).  The check keeps its verdict in a slot of a static array
+ * per device (4096 slots, one per call in turn); a call whose slot is taken
+ * by a later call before its kernels run falls back to the table form.
+ * Errors: RX_EINVAL, RX_ENOTUPLOADED, RX_EHIP.
  */
 int rx_match(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d_offsets, int64_t n,
              uint8_t* d_out, void* stream);

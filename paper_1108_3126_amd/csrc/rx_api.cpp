@@ -1,6 +1,7 @@
 // C interface of the lockstep matcher: program lifetime, upload and launch
 // selection.  Every entry point catches everything and reports through a
 // thread-local message.
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <exception>
@@ -176,6 +177,21 @@ int rx_match_ex(const rx_program* prog, const uint8_t* d_bytes, const int64_t* d
         a.block = launch->block;
         a.grid = launch->grid;
         a.unroll = launch->unroll;
+    }
+    if (variant == RX_VARIANT_AUTO && n >= kLayoutMinStrings && jit_offsets_ready(P)) {
+        // Equal-length consecutive strings go to the bit-sliced kernel: a
+        // check on the device fills this call's layout slot, the sliced kernel
+        // runs if the slot says so, and the table-form launch below does
+        // nothing in that case (and everything otherwise).
+        static std::atomic<int64_t> next_id{0};
+        const int64_t id = ++next_id;
+        int64_t* slot = nullptr;
+        if (int e = layout_slot(id, &slot)) return hip_fail(e, "layout slot");
+        if (int e = launch_layout_check(d_offsets, n, d_bytes, slot, id, stream)) return hip_fail(e, "layout check");
+        if (int e = launch_sliced_offsets(P, d_bytes, slot, id, n, d_out, stream))
+            return hip_fail(e, "kernel launch (sliced)");
+        a.skip = slot;
+        a.skip_id = id;
     }
     if (variant == RX_VARIANT_AUTO) variant = P->W <= kLaneMaxWords ? RX_VARIANT_LANE : RX_VARIANT_WAVE;
     int e;

@@ -201,14 +201,34 @@ struct LaunchArgs {
     uint32_t* rows_out = nullptr;
     int64_t rows_len = 0, rows_cl = 0;
     int32_t rows_per_chunk = 0;
+    // rx_match's layout slot (see launch_layout_check): nothing runs when the
+    // bit-sliced kernel took the strings
+    const int64_t* skip = nullptr;
+    int64_t skip_id = 0;
 };
 int launch_lane(const LaunchArgs& a);
+// Equal-length consecutive strings for rx_match (rx_kernels.hip): the slot of
+// call `id` in a static per-device array of kLayoutSlots slots of four int64
+// {id, length, first offset, flaw}; launch_layout_check fills it on `stream`
+// (flaw 0: string i is bytes[first + i * length, + length), length a multiple
+// of 16 up to kLayoutMaxLength and the first byte 16-byte aligned).
+constexpr int64_t kLayoutSlots = 4096;
+constexpr int64_t kLayoutMaxLength = (int64_t)1 << 26;
+constexpr int64_t kLayoutMinStrings = 16384;   // fewer strings: the table form alone
+int layout_slot(int64_t id, int64_t** slot);
+int launch_layout_check(const int64_t* offsets, int64_t n, const uint8_t* bytes, int64_t* slot, int64_t id,
+                        void* stream);
 // bit-sliced node circuit (rx_jit.cpp)
 std::string jit_step_source(const Program& P, int* n_state, int* n_ops);
 std::string jit_full_source(const Program& P, int* n_state, int* n_ops);
 int jit_compile(Program* P, const char* arch);
 void jit_free(Program* P);
 bool jit_ready(const Program* P, int* n_state, int* n_ops);
+// rx_match's equal-length strings through the skewed kernel (the layout slot
+// of call id decides whether it runs)
+bool jit_offsets_ready(const Program* P);
+int launch_sliced_offsets(const Program* P, const uint8_t* bytes, const int64_t* slot, int64_t id, int64_t n,
+                          uint8_t* out, void* stream);
 // staged[u] for staging modes u = 0..5 (see rx_program_jit_staging).
 void jit_staging(const Program* P, int32_t staged[7]);
 // Plane-form circuits (rx_jit.cpp): one module per list of programs.

@@ -805,6 +805,24 @@ extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_fixed_skew_w(cons
     rx_skew<false, false>(bytes, length, n, out, nullptr, rx_tile);
 }
 
+// rx_match's equal-length strings: the layout slot of call `id` (see the
+// layout check: {id, length, first offset, flaw}) holds the length and the
+// first string's offset; the kernel does nothing unless the slot is this
+// call's and has no flaw (the table form then matches the strings).
+extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_offsets_skew(const unsigned char* __restrict__ bytes,
+        const long long* __restrict__ slot, long long id, long long n, unsigned char* __restrict__ out) {
+    extern __shared__ u32 rx_tile[];
+    if (slot[0] != id || slot[3] != 0) return;
+    rx_skew<true, false>(bytes + slot[2], slot[1], n, out, nullptr, rx_tile);
+}
+
+extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_offsets_skew_w(const unsigned char* __restrict__ bytes,
+        const long long* __restrict__ slot, long long id, long long n, unsigned char* __restrict__ out) {
+    extern __shared__ u32 rx_tile[];
+    if (slot[0] != id || slot[3] != 0) return;
+    rx_skew<false, false>(bytes + slot[2], slot[1], n, out, nullptr, rx_tile);
+}
+
 // Earliest accepting prefix of every string (the root is not nullable:
 // the caller answers 0 for every string otherwise).
 extern "C" __global__ __launch_bounds__(128, 1) void rx_sliced_first_skew(const unsigned char* __restrict__ bytes,
@@ -1000,6 +1018,7 @@ struct JitKernel {
     hipFunction_t split = nullptr;
     hipFunction_t skew = nullptr;
     bool skew_words = false;   // skew is the single-dword-read form
+    hipFunction_t skew_offsets = nullptr;   // the same form for rx_match's equal-length strings
     hipFunction_t first = nullptr;   // the skewed kernel's earliest-accept form
     bool first_words = false;
     int dev = -1;
@@ -1197,9 +1216,18 @@ int jit_compile(Program* P, const char* arch_in) {
         if (isa_check_agpr_staging(code, arch, kStagedKernels[k], &v, nullptr) != 0) {
             K->guard_ran = 0;   // the check could not run: every staged kernel is dropped
             K->guard_violations[k] = -1;
-        } else {
-            K->guard_violations[k] = v;
+            continue;
         }
+        // the skewed kernels' twins for rx_match's equal-length strings are
+        // checked with them (and dropped with them)
+        const char* twin = k == 3 ? "rx_sliced_offsets_skew" : k == 4 ? "rx_sliced_offsets_skew_w" : nullptr;
+        int vt = 0;
+        if (twin && isa_check_agpr_staging(code, arch, twin, &vt, nullptr) != 0) {
+            K->guard_ran = 0;
+            K->guard_violations[k] = -1;
+            continue;
+        }
+        K->guard_violations[k] = v + vt;
     }
     if (dev >= 0) {
         hipError_t e = hipModuleLoadData(&K->mod, code.data());
@@ -1208,9 +1236,11 @@ int jit_compile(Program* P, const char* arch_in) {
         if (e == hipSuccess) e = hipModuleGetFunction(&K->fixed64, K->mod, "rx_sliced_fixed_pf");
         if (e == hipSuccess) e = hipModuleGetFunction(&K->duo, K->mod, "rx_sliced_fixed_duo");
         if (e == hipSuccess) e = hipModuleGetFunction(&K->split, K->mod, "rx_sliced_fixed_split");
-        hipFunction_t skew_w = nullptr, first_w = nullptr;
+        hipFunction_t skew_w = nullptr, first_w = nullptr, off = nullptr, off_w = nullptr;
         if (e == hipSuccess) e = hipModuleGetFunction(&K->skew, K->mod, "rx_sliced_fixed_skew");
         if (e == hipSuccess) e = hipModuleGetFunction(&skew_w, K->mod, "rx_sliced_fixed_skew_w");
+        if (e == hipSuccess) e = hipModuleGetFunction(&off, K->mod, "rx_sliced_offsets_skew");
+        if (e == hipSuccess) e = hipModuleGetFunction(&off_w, K->mod, "rx_sliced_offsets_skew_w");
         if (e == hipSuccess) e = hipModuleGetFunction(&K->first, K->mod, "rx_sliced_first_skew");
         if (e == hipSuccess) e = hipModuleGetFunction(&first_w, K->mod, "rx_sliced_first_skew_w");
         if (e != hipSuccess) {
@@ -1234,7 +1264,16 @@ int jit_compile(Program* P, const char* arch_in) {
                 K->guard_dropped |= 1 << k;
             }
         }
+        // the twins share their kernel's fate: no scratch and the static check passed
+        for (hipFunction_t* t : {&off, &off_w}) {
+            int scratch = 1;
+            if (hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, *t) != hipSuccess || scratch != 0)
+                *t = nullptr;
+        }
+        if (!K->skew) off = nullptr;
+        if (!skew_w) off_w = nullptr;
         K->skew_words = !K->skew && skew_w;
+        K->skew_offsets = K->skew ? off : off_w;
         if (!K->skew) K->skew = skew_w;   // the skewed kernel with single-dword transposer reads
         K->first_words = !K->first && first_w;
         if (!K->first) K->first = first_w;
@@ -1303,6 +1342,26 @@ int launch_sliced_first(const Program* P, const uint8_t* bytes, int64_t length, 
     void* args[] = {&b, &len, &nn, &f};
     return (int)hipModuleLaunchKernel(K->first, (unsigned)grid, 1, 1, 128, 1, 1, lds, (hipStream_t)stream, args,
                                       nullptr);
+}
+
+bool jit_offsets_ready(const Program* P) {
+    const JitKernel* K = static_cast<const JitKernel*>(P->jit);
+    return K && K->skew_offsets;
+}
+
+int launch_sliced_offsets(const Program* P, const uint8_t* bytes, const int64_t* slot, int64_t id, int64_t n,
+                          uint8_t* out, void* stream) {
+    const JitKernel* K = static_cast<const JitKernel*>(P->jit);
+    if (!K || !K->skew_offsets) return (int)hipErrorInvalidValue;
+    const long long grid = (n + 2047) / 2048;
+    const unsigned lds = 2048 * 32 + 2 * 2048 * 4;
+    long long i = id, nn = n;
+    const void* b = bytes;
+    const void* sl = slot;
+    void* o = out;
+    void* args[] = {&b, &sl, &i, &nn, &o};
+    return (int)hipModuleLaunchKernel(K->skew_offsets, (unsigned)grid, 1, 1, 128, 1, 1, lds, (hipStream_t)stream,
+                                      args, nullptr);
 }
 
 int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,

@@ -49,7 +49,17 @@ struct KArgs {
     uint32_t* rows_out;
     int64_t rows_len, rows_cl;
     int32_t rows_per_chunk, rows_pad;
+    // rx_match's layout slot: the kernel does nothing when the slot holds
+    // skip_id and no flaw (the bit-sliced kernel has matched the strings)
+    const int64_t* skip;
+    int64_t skip_id;
 };
+
+// true when the layout check of this call found equal lengths and the
+// bit-sliced kernel took the strings
+__device__ __forceinline__ bool taken_by_sliced(const KArgs& a) {
+    return a.skip && a.skip[0] == a.skip_id && a.skip[3] == 0;
+}
 
 // Start and byte range of row j of the chunk-parallel run.
 __device__ __forceinline__ void row_span(const KArgs& a, int64_t j, int* r, int64_t* lo, int64_t* hi) {
@@ -107,6 +117,7 @@ __device__ __forceinline__ void lane_step(uint32_t (&S)[W], uint32_t c, const ui
 // is in S after the first k bytes (k = 0: the root is nullable), or -1.
 template <int W, bool FIRST, bool ROWS>
 __global__ __launch_bounds__(256) void k_lane(KArgs a) {
+    if (taken_by_sliced(a)) return;
     extern __shared__ uint32_t lds[];
     uint32_t* M = lds;
     uint32_t* F = lds + 256 * W;
@@ -173,6 +184,7 @@ __global__ __launch_bounds__(256) void k_lane(KArgs a) {
 // One wavefront per string.  Lane j owns words j and j + 64 of the set.
 template <bool TABLES_IN_LDS, bool FIRST, bool ROWS>
 __global__ __launch_bounds__(1024) void k_wave(KArgs a) {
+    if (taken_by_sliced(a)) return;
     extern __shared__ uint32_t lds[];
     const int W = a.W, L = a.L;
     const uint32_t* M = a.bytemask;
@@ -292,6 +304,7 @@ __global__ __launch_bounds__(1024) void k_wave(KArgs a) {
 // per byte (the partials alternate between two LDS buffers).
 template <bool TABLES_IN_LDS, int WS>
 __global__ __launch_bounds__(64 * WS) void k_wave_split(KArgs a) {
+    if (taken_by_sliced(a)) return;
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t part[2][WS][kWaveMaxWords];
     const int W = a.W, L = a.L;
@@ -411,6 +424,8 @@ KArgs kargs(const LaunchArgs& a) {
     k.rows_cl = a.rows_cl;
     k.rows_per_chunk = a.rows_per_chunk;
     k.rows_pad = 0;
+    k.skip = a.skip;
+    k.skip_id = a.skip_id;
     return k;
 }
 
@@ -731,6 +746,66 @@ int long_scratch(void** ptr) {
     }
     *ptr = it->second;
     return 0;
+}
+
+// Layout check of rx_match's strings, so that equal-length consecutive
+// strings can go to the bit-sliced kernel without the host reading the
+// offsets.  Each call takes the slot of its id (id modulo the slot count) in
+// a static array per device: {id, length, first offset, flaw}.  The readers
+// of a slot act only while it holds their id, so a later call that takes the
+// same slot sends the earlier call's strings to the table form, which gives
+// the same bits; ids only grow, so once a reader has seen another id every
+// later reader of that call sees one too.
+static __device__ __align__(256) int64_t layout_slots[kLayoutSlots * 4];
+
+namespace {
+__global__ void k_layout_begin(const int64_t* __restrict__ offsets, int64_t n, const uint8_t* bytes, int64_t* slot,
+                               int64_t id) {
+    const int64_t o0 = offsets[0], len = offsets[1] - o0;
+    const bool ok = len > 0 && (len & 15) == 0 && len <= kLayoutMaxLength && offsets[n] - o0 == n * len &&
+                    (reinterpret_cast<uintptr_t>(bytes + o0) & 15) == 0;
+    slot[1] = len;
+    slot[2] = o0;
+    slot[3] = ok ? 0 : 1;
+    slot[0] = id;
+}
+
+__global__ __launch_bounds__(256) void k_layout_check(const int64_t* __restrict__ offsets, int64_t n,
+                                                      int64_t* slot, int64_t id) {
+    if (slot[0] != id || slot[3] != 0) return;
+    const int64_t len = slot[1], o0 = slot[2];
+    bool flaw = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x)
+        flaw |= offsets[i] != o0 + i * len;
+    if (__any(flaw) && (threadIdx.x & 63) == 0)
+        atomicOr(reinterpret_cast<unsigned long long*>(slot + 3), 1ull);
+}
+}  // namespace
+
+int layout_slot(int64_t id, int64_t** slot) {
+    static std::mutex mu;
+    static std::unordered_map<int, int64_t*> by_device;
+    int dev = -1;
+    if (hipError_t e = hipGetDevice(&dev)) return (int)e;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = by_device.find(dev);
+    if (it == by_device.end()) {
+        void* p = nullptr;
+        if (hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(layout_slots))) return (int)e;
+        if (!p) return (int)hipErrorInvalidSymbol;
+        it = by_device.emplace(dev, static_cast<int64_t*>(p)).first;
+    }
+    *slot = it->second + (id % kLayoutSlots) * 4;
+    return 0;
+}
+
+int launch_layout_check(const int64_t* offsets, int64_t n, const uint8_t* bytes, int64_t* slot, int64_t id,
+                        void* stream) {
+    hipLaunchKernelGGL(k_layout_begin, dim3(1), dim3(1), 0, (hipStream_t)stream, offsets, n, bytes, slot, id);
+    const int64_t blocks = (n + 1 + 255) / 256;
+    hipLaunchKernelGGL(k_layout_check, dim3((unsigned)(blocks < 2048 ? blocks : 2048)), dim3(256), 0,
+                       (hipStream_t)stream, offsets, n, slot, id);
+    return (int)hipGetLastError();
 }
 
 int hip_current_device(int* dev) { return (int)hipGetDevice(dev); }
