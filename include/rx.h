@@ -409,6 +409,20 @@ int rx_program_jit_staging(const rx_program* prog, int32_t staged[7]);
  * shows what runs instead).  Errors: RX_EINVAL (NULL arguments). */
 int rx_program_jit_guard(const rx_program* prog, int32_t* ran, int32_t violations[8], int32_t* dropped);
 
+/* The run-time check rx_program_jit makes on a device (after the static
+ * check): every kept bit-sliced kernel matches a seeded batch (4,096 strings
+ * of 256 bytes that walk the automaton, mostly through bytes a live leaf's
+ * label holds) and its bits are compared with the table step of Def. 5.1
+ * computed on the host (accept bits; first accepting prefixes for the
+ * earliest-accept kernels of non-nullable programs).  *ran = 1 when the check
+ * ran (0 before rx_program_jit or when the circuit was only compiled);
+ * *dropped has bit k set when staged kernel k (the order of
+ * rx_program_jit_guard) gave other bits and was dropped (the staging report
+ * shows what runs instead).  The LDS-staged kernel is checked too; if it
+ * disagrees, rx_program_jit fails with RX_EJIT.  Errors: RX_EINVAL (NULL
+ * arguments). */
+int rx_program_jit_selfcheck(const rx_program* prog, int32_t* ran, int32_t* dropped);
+
 /* Generates and compiles the plane-form circuits of a list of programs, for
  * rx_match_multi with RX_FORM_PLANES on that list (same programs, same
  * order): one module holding every program's circuit (the per-node processes

@@ -836,6 +836,12 @@ int rx_program_jit_guard(const rx_program* prog, int32_t* ran, int32_t violation
     return RX_OK;
 }
 
+int rx_program_jit_selfcheck(const rx_program* prog, int32_t* ran, int32_t* dropped) {
+    if (!prog || !ran || !dropped) return fail(RX_EINVAL, "NULL argument");
+    jit_selfcheck_report(reinterpret_cast<const Program*>(prog), ran, dropped);
+    return RX_OK;
+}
+
 int rx_isa_check_staging(const void* code, size_t len, const char* arch, const char* kernel, int32_t* violations) {
     RX_GUARD_BEGIN
     if (!code || !arch || !kernel || !violations) return fail(RX_EINVAL, "NULL argument");

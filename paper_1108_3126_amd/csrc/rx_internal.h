@@ -249,6 +249,7 @@ int isa_check_agpr_staging(const std::vector<char>& code, const std::string& arc
                            int* violations, std::string* example);
 // The check's outcome for a program's kernels (see rx_program_jit_guard).
 void jit_guard(const Program* P, int32_t* ran, int32_t violations[8], int32_t* dropped);
+void jit_selfcheck_report(const Program* P, int32_t* ran, int32_t* dropped);
 // The staging mode that unroll = 0 selects.
 int jit_default_staging(const Program* P);
 // The skewed kernel's earliest-accept form (kept unless it spills) and its launch.

@@ -1030,6 +1030,10 @@ struct JitKernel {
     int guard_ran = 0;
     int guard_violations[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
     int guard_dropped = 0;   // bit k: kernel k was dropped by the check
+    // run-time check (jit_selfcheck): 1 when it ran on the device; bit k of
+    // selfcheck_dropped: staged kernel k gave other bits than the table step
+    int selfcheck_ran = 0;
+    int selfcheck_dropped = 0;
 };
 
 // The kernels that keep in-flight loads in accumulation registers.
@@ -1193,6 +1197,167 @@ int launch_planes_circuits(const Program* const* progs, int n, const uint32_t* p
     return (int)hipModuleLaunchKernel(K->fn, grid, 1, 1, 64, 1, 1, 0, (hipStream_t)stream, args, nullptr);
 }
 
+namespace {
+// A seeded batch for the run-time check of the staged kernels: strings that
+// walk the automaton (each byte, with probability 7/8, one that a live leaf's
+// label holds, so accepts are reached and left), and the table step of
+// Def. 5.1 on the host over them: S = First, then S' = union of Follow[x]
+// over the leaves x in S whose label holds the byte; the accept bit is rank L.
+struct SelfCheckBatch {
+    int64_t n = 0, length = 0;
+    std::vector<uint8_t> bytes;
+    std::vector<uint8_t> accept;    // accept bit after the last byte
+    std::vector<int64_t> first;     // fewest bytes after which the accept bit is set, or -1
+};
+
+SelfCheckBatch selfcheck_batch(const Program& P, int64_t n, int64_t length) {
+    SelfCheckBatch B;
+    B.n = n;
+    B.length = length;
+    B.bytes.resize((size_t)(n * length));
+    B.accept.resize((size_t)n);
+    B.first.resize((size_t)n);
+    const int W = P.W, L = P.L;
+    std::vector<std::vector<uint8_t>> label_bytes((size_t)L);
+    for (int b = 0; b < 256; ++b)
+        for (int r = 0; r < L; ++r)
+            if ((P.bytemask[(size_t)b * W + (r >> 5)] >> (r & 31)) & 1u) label_bytes[(size_t)r].push_back((uint8_t)b);
+    uint64_t z = 0x243f6a8885a308d3ull;   // splitmix64 (Steele, Lea, Flood 2014)
+    auto next = [&z]() {
+        uint64_t x = (z += 0x9e3779b97f4a7c15ull);
+        x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+        x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+        return x ^ (x >> 31);
+    };
+    std::vector<uint32_t> S((size_t)W), T((size_t)W);
+    std::vector<int> live;
+    const bool acc0 = (P.first[(size_t)(L >> 5)] >> (L & 31)) & 1u;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int w = 0; w < W; ++w) S[(size_t)w] = P.first[(size_t)w];
+        int64_t firstpos = acc0 ? 0 : -1;
+        for (int64_t k = 0; k < length; ++k) {
+            live.clear();
+            for (int w = 0; w < W; ++w)
+                for (uint32_t x = S[(size_t)w]; x; x &= x - 1) {
+                    const int r = w * 32 + __builtin_ctz(x);
+                    if (r < L && !label_bytes[(size_t)r].empty()) live.push_back(r);
+                }
+            uint8_t c;
+            const uint64_t u = next();
+            if (live.empty() || (u & 7) == 0) {
+                c = (uint8_t)(u >> 8);
+            } else {
+                const auto& lb = label_bytes[(size_t)live[(size_t)((u >> 8) % live.size())]];
+                c = lb[(size_t)((u >> 32) % lb.size())];
+            }
+            B.bytes[(size_t)(i * length + k)] = c;
+            std::fill(T.begin(), T.end(), 0u);
+            for (int w = 0; w < W; ++w) {
+                uint32_t x = S[(size_t)w] & P.bytemask[(size_t)c * W + w];
+                while (x) {
+                    const int r = w * 32 + __builtin_ctz(x);
+                    x &= x - 1;
+                    if (r >= L) continue;
+                    for (int v = 0; v < W; ++v) T[(size_t)v] |= P.follow[(size_t)r * W + v];
+                }
+            }
+            S.swap(T);
+            if (firstpos < 0 && ((S[(size_t)(L >> 5)] >> (L & 31)) & 1u)) firstpos = k + 1;
+        }
+        B.accept[(size_t)i] = (uint8_t)((S[(size_t)(L >> 5)] >> (L & 31)) & 1u);
+        B.first[(size_t)i] = firstpos;
+    }
+    return B;
+}
+
+// Runs every kept register-staged kernel of K (and the LDS-staged one) on the
+// batch; a staged kernel whose bits differ from the table step is dropped.
+// Returns nonzero when the check itself could not run or the LDS-staged
+// kernel disagrees.
+int jit_selfcheck(const Program& P, JitKernel* K, hipFunction_t* const* staged, int n_staged,
+                  hipFunction_t* offsets_twin, hipFunction_t* offsets_twin_w) {
+    const int64_t n = 4096, length = 256;
+    const SelfCheckBatch B = selfcheck_batch(P, n, length);
+    uint8_t* d_bytes = nullptr;
+    uint8_t* d_out = nullptr;
+    int64_t* d_first = nullptr;
+    int64_t* d_slot = nullptr;
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&d_bytes, (size_t)(n * length));
+    if (e == hipSuccess) e = hipMalloc(&d_out, (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&d_first, 8 * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&d_slot, 4 * sizeof(int64_t));
+    const int64_t slot[4] = {1, length, 0, 0};   // an equal-length batch, as the layout check would find it
+    if (e == hipSuccess) e = hipMemcpy(d_bytes, B.bytes.data(), (size_t)(n * length), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_slot, slot, sizeof(slot), hipMemcpyHostToDevice);
+    std::vector<uint8_t> out((size_t)n);
+    std::vector<int64_t> fp((size_t)n);
+    // threads, LDS bytes and output of each kernel form
+    auto run = [&](hipFunction_t f, int threads, unsigned lds, int kind) -> int {
+        // kind 0: accept bits (bytes, length, n, out); 1: earliest accepts; 2: the offsets twin
+        long long len = length, nn = n, id = 1;
+        const void* b = d_bytes;
+        void* o = d_out;
+        void* fo = d_first;
+        const void* sl = d_slot;
+        void* a0[] = {&b, &len, &nn, &o};
+        void* a1[] = {&b, &len, &nn, &fo};
+        void* a2[] = {&b, &sl, &id, &nn, &o};
+        hipError_t r = hipMemsetAsync(kind == 1 ? (void*)d_first : (void*)d_out, 0xff,
+                                      kind == 1 ? 8 * (size_t)n : (size_t)n, st);
+        if (r == hipSuccess)
+            r = hipModuleLaunchKernel(f, (unsigned)((n + 2047) / 2048), 1, 1, threads, 1, 1, lds, st,
+                                      kind == 0 ? a0 : kind == 1 ? a1 : a2, nullptr);
+        if (r == hipSuccess) r = hipStreamSynchronize(st);
+        if (r == hipSuccess && kind != 1) r = hipMemcpy(out.data(), d_out, (size_t)n, hipMemcpyDeviceToHost);
+        if (r == hipSuccess && kind == 1) r = hipMemcpy(fp.data(), d_first, 8 * (size_t)n, hipMemcpyDeviceToHost);
+        if (r != hipSuccess) return -1;
+        if (kind == 1) return fp == B.first ? 0 : 1;
+        return out == B.accept ? 0 : 1;
+    };
+    int rc = e == hipSuccess ? 0 : -1;
+    if (!rc && K->fixed) {
+        const int bad = run(K->fixed, 64, 2048 * 32, 0);
+        if (bad) rc = bad < 0 ? -1 : -2;
+    }
+    if (!rc) {
+        // staged kernels in the order of kStagedKernels: modes 1, 3, 4, 5 (pairs), 5 (words), earliest (pairs, words)
+        const int threads[7] = {64, 128, 128, 128, 128, 128, 128};
+        const unsigned lds[7] = {2048 * 32, 2048 * 32, 2048 * 32 + 2 * 2048 * 4, 2048 * 32 + 2 * 2048 * 4,
+                                 2048 * 32 + 2 * 2048 * 4, 2048 * 32 + 2 * 2048 * 4, 2048 * 32 + 2 * 2048 * 4};
+        for (int k = 0; k < n_staged && !rc; ++k) {
+            hipFunction_t* f = staged[k];
+            // the earliest-accept kernels serve programs whose root is not
+            // nullable (the caller answers 0 for every string otherwise)
+            if (!*f || (k >= 5 && P.nullable)) continue;
+            const int bad = run(*f, threads[k], lds[k], k >= 5 ? 1 : 0);
+            if (bad < 0) rc = -1;
+            if (bad > 0) {
+                *f = nullptr;
+                K->selfcheck_dropped |= 1 << k;
+            }
+        }
+        for (hipFunction_t* t : {offsets_twin, offsets_twin_w}) {
+            if (rc || !*t) continue;
+            const int bad = run(*t, 128, 2048 * 32 + 2 * 2048 * 4, 2);
+            if (bad < 0) rc = -1;
+            if (bad > 0) {
+                *t = nullptr;
+                K->selfcheck_dropped |= 1 << (t == offsets_twin ? 3 : 4);   // reported with its kernel
+            }
+        }
+    }
+    if (d_bytes) (void)hipFree(d_bytes);
+    if (d_out) (void)hipFree(d_out);
+    if (d_first) (void)hipFree(d_first);
+    if (d_slot) (void)hipFree(d_slot);
+    if (st) (void)hipStreamDestroy(st);
+    if (!rc) K->selfcheck_ran = 1;
+    return rc;
+}
+}  // namespace
+
 int jit_compile(Program* P, const char* arch_in) {
     int ns = 0, nops = 0;
     const std::string src = jit_full_source(*P, &ns, &nops);
@@ -1272,6 +1437,21 @@ int jit_compile(Program* P, const char* arch_in) {
         }
         if (!K->skew) off = nullptr;
         if (!skew_w) off_w = nullptr;
+        // Every kernel that is kept runs once on a seeded batch against the
+        // table step; one that gives other bits is dropped as well.
+        const int sc = jit_selfcheck(*P, K, staged, kNumStaged, &off, &off_w);
+        if (sc == -2) {
+            hipModuleUnload(K->mod);
+            delete K;
+            return fail(RX_EJIT, "the bit-sliced kernel gives other bits than the table step on the check batch");
+        }
+        if (sc != 0) {
+            hipModuleUnload(K->mod);
+            delete K;
+            return fail(RX_EHIP, "the run-time check of the bit-sliced kernels could not run");
+        }
+        if (!K->skew) off = nullptr;
+        if (!skew_w) off_w = nullptr;
         K->skew_words = !K->skew && skew_w;
         K->skew_offsets = K->skew ? off : off_w;
         if (!K->skew) K->skew = skew_w;   // the skewed kernel with single-dword transposer reads
@@ -1316,6 +1496,12 @@ void jit_staging(const Program* P, int32_t staged[7]) {
     staged[4] = K->split ? 1 : 0;
     staged[5] = K->skew ? (K->skew_words ? 2 : 1) : 0;
     staged[6] = K->first ? (K->first_words ? 2 : 1) : 0;
+}
+
+void jit_selfcheck_report(const Program* P, int32_t* ran, int32_t* dropped) {
+    const JitKernel* K = static_cast<const JitKernel*>(P->jit);
+    *ran = K ? K->selfcheck_ran : 0;
+    *dropped = K ? K->selfcheck_dropped : 0;
 }
 
 void jit_guard(const Program* P, int32_t* ran, int32_t violations[8], int32_t* dropped) {

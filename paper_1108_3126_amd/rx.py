@@ -104,6 +104,7 @@ SIGNATURES = {
     "rx_program_jit_stats": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "rx_program_jit_staging": (ctypes.c_int, [_VP, ctypes.POINTER(_I32)]),
     "rx_program_jit_guard": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "rx_program_jit_selfcheck": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "rx_match_multi_prepare": (ctypes.c_int, [ctypes.POINTER(_VP), _I32, ctypes.c_char_p, ctypes.POINTER(_I32)]),
     "rx_program_jit_planes_source": (ctypes.c_int, [_VP, ctypes.c_char_p, _SZ, ctypes.POINTER(_SZ)]),
     "rx_isa_check_staging": (ctypes.c_int, [ctypes.c_char_p, _SZ, ctypes.c_char_p, ctypes.c_char_p,
@@ -311,6 +312,12 @@ class Program:
         v = (ctypes.c_int32 * 8)()
         _check(lib().rx_program_jit_guard(self._h, ctypes.byref(ran), v, ctypes.byref(dropped)))
         return {"ran": ran.value, "violations": list(v)[:7], "dropped": dropped.value}
+
+    def jit_selfcheck(self):
+        """The run-time check of the bit-sliced kernels against the table step: {"ran", "dropped"}."""
+        ran, dropped = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().rx_program_jit_selfcheck(self._h, ctypes.byref(ran), ctypes.byref(dropped)))
+        return {"ran": ran.value, "dropped": dropped.value}
 
     # -- device -----------------------------------------------------------
     def upload(self, device=None, stream=None):

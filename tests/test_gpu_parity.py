@@ -232,6 +232,15 @@ def test_sliced_single_program(dev):
         if guard["dropped"] >> k & 1:
             assert staging[mode] == 0
     assert guard["violations"][3] == 0 and not guard["dropped"] & 8   # the default kernel passed
+    # the run-time check ran every kept kernel against the table step on a seeded batch; a kernel
+    # it dropped no longer shows in the staging report
+    check = p.jit_selfcheck()
+    print("sliced single: run-time check", check, flush=True)
+    assert check["ran"] == 1
+    for k, mode in enumerate((1, 3, 4)):
+        if check["dropped"] >> k & 1:
+            assert staging[mode] == 0
+    assert not check["dropped"] & 8   # the default kernel agreed
     want = oracle_match(prog, s)
     print("sliced single: accepted", int(want.sum()), flush=True)
     for v in (rx.VARIANT_SLICED, rx.VARIANT_LANE, rx.VARIANT_WAVE, 0):
