@@ -366,7 +366,12 @@ int rx_match_fixed_ex(const rx_program* prog, const uint8_t* d_bytes, int64_t le
  * without a device only checks that the generated source builds.
  * Programs whose circuit keeps more than 160 leaf states are refused with
  * RX_ETOOBIG (they would not fit in registers); the table-form kernels run
- * them.  Errors: RX_EJIT (message holds the compiler log), RX_ETOOBIG, RX_EHIP.
+ * them.  When the code object is loaded, every kernel kept is run once on a
+ * seeded batch and checked against the table step (rx_program_jit_selfcheck):
+ * the call then allocates about 1.1 MB of device memory for that batch, frees
+ * it, and waits for the check to finish (synchronous; not for capture).
+ * Errors: RX_EJIT (message holds the compiler log, or the LDS-staged kernel
+ * disagreed with the table step), RX_ETOOBIG, RX_EHIP.
  */
 int rx_program_jit(rx_program* prog, const char* arch);
 
