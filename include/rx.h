@@ -192,9 +192,10 @@ int rx_program_upload(rx_program* prog, void* d_buf, size_t cap, void* stream);
  * must satisfy 0 <= offsets[i] <= offsets[i+1] (not checked on the device).
  * d_out[i] is set to 1 if string i is in the language (a substring of it, for
  * RX_SEARCH), else 0.  Runs asynchronously on `stream`; allocates nothing.
- * n == 0 is a no-op.  The kernel variant is chosen from the program's size:
- * one lane per string for sets of up to 16 words, one wavefront per string
- * above that.  When the program's bit-sliced circuit is compiled
+ * n == 0 is a no-op.  The kernel variant is chosen from the program's size
+ * and the string count: wavefronts per string for sets above 16 words, and
+ * for sets of 6-16 words when the strings number at most four per SIMD
+ * (16 x compute units); otherwise one lane per string.  When the program's bit-sliced circuit is compiled
  * (rx_program_jit) and n >= 16384, a check on the device decides whether the
  * strings are equal-length and consecutive (offsets[i] = offsets[0] + i * len,
  * len a multiple of 16 up to 2^26, d_bytes + offsets[0] 16-byte aligned); if
@@ -230,10 +231,11 @@ typedef struct {
                                waves' requests alternate (default).  A program whose staged kernels (1, 3, 4,
                                5) would spill registers runs 2 instead; 5 needs length <= 2^26 (else 4).
                                0 = 5 when its kernel was kept, else 3, else 2.
-                               wave: wavefronts per string, 1, 2 or 4 (each takes every 2nd or 4th
-                               survivor word and the partial next sets meet in LDS once per byte);
-                               0 = 4 when the strings number at most a quarter of the SIMDs, 2 when at
-                               most half, else 1. */
+                               wave: wavefronts per string, 1, 2, 4, 8 or 16 (each takes every 2nd ...
+                               16th survivor word and the partial next sets meet in LDS once per byte);
+                               0 = the most that leave every wavefront at least three set words and
+                               put at most four wavefronts on a SIMD (strings x wavefronts <= 4 x SIMDs),
+                               else 1. */
 } rx_launch;
 
 /* Earliest accepting prefix (the accept bit's first appearance, Def. 5.3

@@ -122,8 +122,8 @@ int autotune_single(const Program* P, const uint8_t* d_bytes, const int64_t* d_o
             for (int gm : {0, 2, 4, 8}) add(RX_VARIANT_LANE, block, gm * cus);
     for (int block : {64, 256, 1024})
         for (int gm : {0, 4}) add(RX_VARIANT_WAVE, block, gm * cus);
-    // lanes per set: 64 (one wavefront per string), 128 or 256 (two or four wavefronts per string)
-    for (int ws : {2, 4}) {
+    // lanes per set: 64 (one wavefront per string) up to 1024 (sixteen wavefronts per string)
+    for (int ws : {2, 4, 8, 16}) {
         add(RX_VARIANT_WAVE, 0, 0);
         cands.back().launch.unroll = ws;
     }

@@ -466,11 +466,15 @@ namespace {
 template <int WS>
 int launch_wave_split(const LaunchArgs& a, size_t lds) {
     const int grid = (int)(a.n < (1 << 30) ? a.n : (1 << 30));
-    if (lds <= 150 * 1024) {
+    // the tables go to LDS when they fit beside the partial sets (2 x WS x 512 bytes)
+    const size_t cap = (size_t)(158 * 1024) - 2 * WS * kWaveMaxWords * 4 < (size_t)(150 * 1024)
+                           ? (size_t)(158 * 1024) - 2 * WS * kWaveMaxWords * 4
+                           : (size_t)(150 * 1024);
+    if (lds <= cap) {
         static bool attr_set = false;
         if (!attr_set) {
             hipFuncSetAttribute((const void*)k_wave_split<true, WS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                150 * 1024);
+                                (int)cap);
             attr_set = true;
         }
         hipLaunchKernelGGL((k_wave_split<true, WS>), dim3(grid), dim3(64 * WS), lds, (hipStream_t)a.stream, kargs(a));
@@ -485,14 +489,24 @@ int launch_wave(const LaunchArgs& a) {
     const size_t lds_tables = 4 * (size_t)(256 + a.L) * a.W;
     if (!a.rows_out && !a.first_pos && a.n > 0) {
         // Few strings: several wavefronts per string keep the SIMDs busy.
-        // rx_launch.unroll picks wavefronts per string (1, 2 or 4; 0 = by count).
+        // rx_launch.unroll picks wavefronts per string (1, 2, 4, 8 or 16; 0 =
+        // the most that leave every wavefront at least three set words and
+        // put at most four wavefronts on a SIMD: the per-byte barrier costs
+        // more than a wavefront with fewer words saves).
         int ws = a.unroll;
         if (ws == 0) {
             int cus = 0;
             if (hip_cu_count(&cus) || cus <= 0) cus = 256;
             const int64_t simds = 4 * (int64_t)cus;
-            ws = a.n * 4 <= simds ? 4 : a.n * 2 <= simds ? 2 : 1;
+            ws = 1;
+            for (int c : {16, 8, 4, 2})
+                if (a.n * c <= 4 * simds && 3 * c <= a.W) {
+                    ws = c;
+                    break;
+                }
         }
+        if (ws == 16) return launch_wave_split<16>(a, lds_tables);
+        if (ws == 8) return launch_wave_split<8>(a, lds_tables);
         if (ws == 4) return launch_wave_split<4>(a, lds_tables);
         if (ws == 2) return launch_wave_split<2>(a, lds_tables);
     }

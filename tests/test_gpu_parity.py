@@ -164,7 +164,7 @@ def test_pathological_4096_nodes(dev, family, k):
 
 @pytest.mark.parametrize("family,k", [("nested", 819), ("altstar", 585), ("nested", 40)])
 def test_wavefronts_per_string(dev, family, k):
-    """One, two or four wavefronts per string (partial next sets meeting in LDS) give the same bits, with
+    """One, two, four, eight or sixteen wavefronts per string (partial next sets meeting in LDS) give the same bits, with
     tables in LDS (nested, 40), through the caches (altstar) and with chunk-union rows (both 4,096-node
     programs); offsets and fixed layouts."""
     from paper_1108_3126_amd import rx
@@ -175,7 +175,7 @@ def test_wavefronts_per_string(dev, family, k):
     assert want[:20].sum() == 0 and want[20:].all()
     p = rx.compile(prog.ast, prog.root).upload(dev)
     d, o = torch.from_numpy(s.data).to(dev), torch.from_numpy(s.offsets).to(dev)
-    for ws in (0, 1, 2, 4):
+    for ws in (0, 1, 2, 4, 8, 16):
         got = rx.match(p, d, o, launch=(rx.VARIANT_WAVE, 0, 0, ws)).cpu().numpy()
         assert np.array_equal(got, want), ws
         got = rx.match_fixed(p, d, 700, s.n, launch=(rx.VARIANT_WAVE, 0, 0, ws)).cpu().numpy()
@@ -195,7 +195,7 @@ def test_wavefronts_per_string_searched(dev):
     s = W.multi_lines(seed=12, n=300, hi=600)
     want = oracle.match(prog.ast, prog.root, prog.classes, True, s.data, s.offsets)
     d, o = torch.from_numpy(s.data).to(dev), torch.from_numpy(s.offsets).to(dev)
-    for ws in (1, 2, 4):
+    for ws in (1, 2, 4, 8, 16):
         assert np.array_equal(rx.match(p, d, o, launch=(rx.VARIANT_WAVE, 0, 0, ws)).cpu().numpy(), want), ws
 
 
