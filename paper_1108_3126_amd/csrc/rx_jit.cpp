@@ -909,8 +909,10 @@ __device__ __forceinline__ void rx_run_slab(const u32* __restrict__ planes, cons
     u32 acc;
     PR::init(st, acc);
     u32 accf = acc;
-    // The registers of a position's planes are refilled with the next tick's
-    // as soon as that position is done, so every load has a whole tick to
+    // Each tick is rx_planes_tick's (four steps, the accept bit kept where a
+    // string still has bytes), with its loads spread through it: the
+    // registers of a position's planes are refilled with the next tick's as
+    // soon as that position is done, so every load has a whole tick to
     // arrive and no second set of registers is needed.  The first tick's
     // values get a use of their own before the loop: the compiler then keeps
     // the loop's loads where they are instead of merging each with the first
