@@ -219,7 +219,8 @@ int layout_slot(int64_t id, int64_t** slot);
 int launch_layout_check(const int64_t* offsets, int64_t n, const uint8_t* bytes, int64_t* slot, int64_t id,
                         void* stream);
 // bit-sliced node circuit (rx_jit.cpp)
-std::string jit_step_source(const Program& P, int* n_state, int* n_ops);
+// (suffix_slot: the state word of a searched program's suffix leaf, or -1)
+std::string jit_step_source(const Program& P, int* n_state, int* n_ops, int* suffix_slot = nullptr);
 std::string jit_full_source(const Program& P, int* n_state, int* n_ops);
 int jit_compile(Program* P, const char* arch);
 void jit_free(Program* P);
@@ -232,16 +233,21 @@ int launch_sliced_offsets(const Program* P, const uint8_t* bytes, const int64_t*
 // staged[u] for staging modes u = 0..5 (see rx_program_jit_staging).
 void jit_staging(const Program* P, int32_t staged[7]);
 // Plane-form circuits (rx_jit.cpp): one module per list of programs.
-std::string jit_multi_planes_source(const Program* const* progs, int n, int* max_state);
+// spec_lds (may be NULL): LDS bytes of the kernel that splits long slabs
+std::string jit_multi_planes_source(const Program* const* progs, int n, int* max_state, int* spec_lds);
+constexpr int64_t kSpecLdsBudget = 140 * 1024;   // checkpoints of a split slab
+constexpr int kSpecCheckpoints = 6;              // after 4, 8, ..., 128 ticks of the second half
 std::string jit_planes_source(const Program& P, int* n_state);   // the list of one program
 // Compiles and loads (once per device and list) the module of `progs`.
 int jit_prepare_planes(const Program* const* progs, int n, const char* arch, int* spill_bytes);
 bool jit_planes_prepared(const Program* const* progs, int n);
 // One wavefront per (program, slab) for the slabs of rank r_lo <= r < r_hi
-// (rank 0 = the longest); returns -1 when the list was not prepared.
+// (rank 0 = the longest), or with split two per (program, slab), the second
+// starting a searched program's slab of 16 ticks or more in the middle (see
+// rx_run_slab_spec); returns -1 when the list was not prepared.
 int launch_planes_circuits(const Program* const* progs, int n, const uint32_t* planes, const int64_t* slab_tick,
                            const int64_t* info, uint32_t* res, int64_t max_slabs, int64_t r_lo, int64_t r_hi,
-                           void* stream);
+                           bool split, void* stream);
 // Static check of a register-staged kernel in a code object (rx_isa_guard.cpp):
 // *violations = instructions not written by the kernel itself that name an
 // accumulation register.  Returns 0 when the check ran, < 0 when it could not.

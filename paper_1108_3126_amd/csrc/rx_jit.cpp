@@ -57,10 +57,25 @@ struct Emitter {
     int ops = 0;
     V zero{0, ""}, one{1, ""};
 
-    V def(const std::string& expr) {
+    std::unordered_map<std::string, std::string> memo;   // expression -> its temporary
+    std::unordered_map<std::string, std::vector<int>> deps;   // temporary -> the state words it reads
+
+    // the state words a value reads (sorted)
+    std::vector<int> reads(const std::string& n) const {
+        if (n.rfind("s[", 0) == 0) return {std::atoi(n.c_str() + 2)};
+        auto it = deps.find(n);
+        return it == deps.end() ? std::vector<int>{} : it->second;
+    }
+    V def(const std::string& expr, const std::string& a, const std::string& b = "") {
+        auto it = memo.find(expr);
+        if (it != memo.end()) return V{-1, it->second};
         const std::string name = "t" + std::to_string(tmp++);
         code << "    const u32 " << name << " = " << expr << ";\n";
         ++ops;
+        memo.emplace(expr, name);
+        std::vector<int> d = reads(a), e = reads(b), u;
+        std::set_union(d.begin(), d.end(), e.begin(), e.end(), std::back_inserter(u));
+        if (!u.empty()) deps.emplace(name, std::move(u));
         return V{-1, name};
     }
     static std::string str(const V& v) {
@@ -73,19 +88,19 @@ struct Emitter {
         if (a.c == 1) return b;
         if (b.c == 1) return a;
         if (a.n == b.n) return a;
-        return def(a.n + " & " + b.n);
+        return a.n < b.n ? def(a.n + " & " + b.n, a.n, b.n) : def(b.n + " & " + a.n, a.n, b.n);
     }
     V OR(const V& a, const V& b) {
         if (a.c == 1 || b.c == 1) return one;
         if (a.c == 0) return b;
         if (b.c == 0) return a;
         if (a.n == b.n) return a;
-        return def(a.n + " | " + b.n);
+        return a.n < b.n ? def(a.n + " | " + b.n, a.n, b.n) : def(b.n + " | " + a.n, a.n, b.n);
     }
     V NOT(const V& a) {
         if (a.c == 0) return one;
         if (a.c == 1) return zero;
-        return def("~" + a.n);
+        return def("~" + a.n, a.n);
     }
 };
 
@@ -170,6 +185,19 @@ int search_prefix_leaf(const Program& P) {
     return dot;
 }
 
+// The search suffix (any byte)* of RX_SEARCH: once its leaf is live it stays
+// live and the string accepts.
+int search_suffix_leaf(const Program& P) {
+    if (search_prefix_leaf(P) < 0) return -1;
+    const int suf = P.c1[0];
+    if (suf < 0 || P.kind[suf] != RX_STAR) return -1;
+    const int dot = P.c0[suf];
+    if (dot < 0 || P.kind[dot] != RX_CLASS) return -1;
+    const auto& c = P.classes[P.label[dot]];
+    if ((c[0] & c[1] & c[2] & c[3]) != ~0ull) return -1;
+    return dot;
+}
+
 std::array<uint64_t, 4> label_set(const Program& P, int p) {
     std::array<uint64_t, 4> s = {0, 0, 0, 0};
     if (P.kind[p] == RX_BYTE) s[P.label[p] >> 6] |= 1ull << (P.label[p] & 63);
@@ -181,7 +209,7 @@ std::array<uint64_t, 4> label_set(const Program& P, int p) {
 
 // Generates the step function (device/host neutral C++): rx_step(s, acc, b0..b7)
 // plus the initial state.  Fills n_state (state words) and n_ops.
-std::string jit_step_source(const Program& P, int* n_state, int* n_ops) {
+std::string jit_step_source(const Program& P, int* n_state, int* n_ops, int* suffix_slot) {
     const int nt = P.n_tree;
     std::vector<char> nu(nt, 0);
     for (int p = nt - 1; p >= 0; --p) {
@@ -196,84 +224,174 @@ std::string jit_step_source(const Program& P, int* n_state, int* n_ops) {
         default: nu[p] = 0; break;
         }
     }
-    const int pre = search_prefix_leaf(P);
-    // state slots for leaves other than the constant prefix leaf
-    std::vector<int> slot(P.m, -1);
+    auto is_first = [&](int r) { return ((P.first[r >> 5] >> (r & 31)) & 1) != 0; };
+    // Leaves that hold the same word at every step share one state word, and
+    // leaves that are constant need none.  The classes are found by partition
+    // refinement: start optimistic (every leaf live at the start is the
+    // constant all-ones, every other the constant zero), write the update of
+    // each leaf in terms of the current classes, and split a class whose
+    // leaves' updates differ (a constant class also loses the leaves whose
+    // update is not that constant); when nothing splits, every leaf of a class
+    // has its start value and its update in common, so by induction over the
+    // steps they agree forever.  Last, a word that the accept bit does not
+    // read, directly or through the updates of words it reads, is dropped
+    // (read as zero): it cannot change the result.
+    constexpr int kOne = -1, kZero = -2, kDead = -3;
+    std::vector<int> grp(P.m, -1), kind;   // leaf -> class; class -> kOne, kZero, kDead or 0 (a word)
+    kind = {kOne, kZero};
+    for (int r = 0; r < P.L; ++r) grp[P.leaf_node[r]] = is_first(r) ? 0 : 1;
+    std::vector<int> slot(P.m, kOne);
     int ns = 0;
-    for (int r = 0; r < P.L; ++r) {
-        const int x = P.leaf_node[r];
-        if (x != pre) slot[x] = ns++;
-    }
-    Emitter E;
-    E.code << "    const u32 nb0 = ~b0, nb1 = ~b1, nb2 = ~b2, nb3 = ~b3, nb4 = ~b4, nb5 = ~b5, nb6 = ~b6, nb7 = ~b7;\n";
-    Decoder D(E);
-    // one decoded mask per distinct label
-    std::vector<std::array<uint64_t, 4>> seen_sets;
-    std::vector<V> seen_vals;
-    std::vector<V> lab(P.m, E.zero);
-    for (int r = 0; r < P.L; ++r) {
-        const int x = P.leaf_node[r];
-        const auto s = label_set(P, x);
-        int found = -1;
-        for (size_t i = 0; i < seen_sets.size(); ++i)
-            if (seen_sets[i] == s) { found = (int)i; break; }
-        if (found < 0) {
-            seen_sets.push_back(s);
-            seen_vals.push_back(D.decode(s));
-            found = (int)seen_vals.size() - 1;
+    auto number = [&]() {
+        std::vector<int> word(kind.size(), -1);
+        ns = 0;
+        for (int r = 0; r < P.L; ++r) {
+            const int x = P.leaf_node[r], g = grp[x];
+            if (kind[g] != 0) slot[x] = kind[g];
+            else {
+                if (word[g] < 0) word[g] = ns++;
+                slot[x] = word[g];
+            }
         }
-        lab[x] = seen_vals[found];
-    }
-    auto state = [&](int x) { return slot[x] < 0 ? E.one : V{-1, "s[" + std::to_string(slot[x]) + "]"}; };
-    std::vector<V> out(nt, E.zero), in(nt, E.zero);
-    for (int p = nt - 1; p >= 0; --p) {
-        const int a = P.c0[p], b = P.c1[p];
-        switch (P.kind[p]) {
-        case RX_BYTE: case RX_CLASS: out[p] = E.AND(state(p), lab[p]); break;
-        case RX_EPS: out[p] = E.zero; break;
-        case RX_CAT: out[p] = E.OR(out[b], nu[b] ? out[a] : E.zero); break;
-        case RX_ALT: out[p] = E.OR(out[a], out[b]); break;
-        case RX_STAR: case RX_PLUS: case RX_OPT: out[p] = out[a]; break;
-        default: break;
+    };
+    number();
+    for (;;) {
+        Emitter E;
+        E.code << "    const u32 nb0 = ~b0, nb1 = ~b1, nb2 = ~b2, nb3 = ~b3, nb4 = ~b4, nb5 = ~b5, nb6 = ~b6, nb7 = ~b7;\n";
+        Decoder D(E);
+        // one decoded mask per distinct label
+        std::vector<std::array<uint64_t, 4>> seen_sets;
+        std::vector<V> seen_vals;
+        std::vector<V> lab(P.m, E.zero);
+        for (int r = 0; r < P.L; ++r) {
+            const int x = P.leaf_node[r];
+            const auto set = label_set(P, x);
+            int found = -1;
+            for (size_t i = 0; i < seen_sets.size(); ++i)
+                if (seen_sets[i] == set) { found = (int)i; break; }
+            if (found < 0) {
+                seen_sets.push_back(set);
+                seen_vals.push_back(D.decode(set));
+                found = (int)seen_vals.size() - 1;
+            }
+            lab[x] = seen_vals[found];
         }
-    }
-    in[0] = E.zero;
-    for (int p = 0; p < nt; ++p) {
-        const int a = P.c0[p], b = P.c1[p];
-        switch (P.kind[p]) {
-        case RX_CAT:
-            in[a] = in[p];
-            in[b] = E.OR(out[a], nu[a] ? in[p] : E.zero);
-            break;
-        case RX_ALT: in[a] = in[p]; in[b] = in[p]; break;
-        case RX_STAR: case RX_PLUS: in[a] = E.OR(in[p], out[a]); break;
-        case RX_OPT: in[a] = in[p]; break;
-        default: break;
+        auto state = [&](int x) {
+            return slot[x] == kOne ? E.one : slot[x] < 0 ? E.zero : V{-1, "s[" + std::to_string(slot[x]) + "]"};
+        };
+        std::vector<V> out(nt, E.zero), in(nt, E.zero);
+        for (int p = nt - 1; p >= 0; --p) {
+            const int a = P.c0[p], b = P.c1[p];
+            switch (P.kind[p]) {
+            case RX_BYTE: case RX_CLASS: out[p] = E.AND(state(p), lab[p]); break;
+            case RX_EPS: out[p] = E.zero; break;
+            case RX_CAT: out[p] = E.OR(out[b], nu[b] ? out[a] : E.zero); break;
+            case RX_ALT: out[p] = E.OR(out[a], out[b]); break;
+            case RX_STAR: case RX_PLUS: case RX_OPT: out[p] = out[a]; break;
+            default: break;
+            }
         }
+        in[0] = E.zero;
+        for (int p = 0; p < nt; ++p) {
+            const int a = P.c0[p], b = P.c1[p];
+            switch (P.kind[p]) {
+            case RX_CAT:
+                in[a] = in[p];
+                in[b] = E.OR(out[a], nu[a] ? in[p] : E.zero);
+                break;
+            case RX_ALT: in[a] = in[p]; in[b] = in[p]; break;
+            case RX_STAR: case RX_PLUS: in[a] = E.OR(in[p], out[a]); break;
+            case RX_OPT: in[a] = in[p]; break;
+            default: break;
+            }
+        }
+        // refine: (class, update) -> class
+        std::vector<int> ngrp(P.m, -1), nkind;
+        std::unordered_map<std::string, int> cls;
+        for (int r = 0; r < P.L; ++r) {
+            const int x = P.leaf_node[r], g = grp[x];
+            const std::string upd = Emitter::str(in[x]);
+            auto it = cls.emplace(std::to_string(g) + ":" + upd, (int)nkind.size());
+            if (it.second) {
+                const bool stays = kind[g] == kDead || (kind[g] == kOne && in[x].c == 1) ||
+                                   (kind[g] == kZero && in[x].c == 0);
+                nkind.push_back(stays ? kind[g] : 0);
+            }
+            ngrp[x] = it.first->second;
+        }
+        bool same = nkind.size() == kind.size();
+        for (int r = 0; same && r < P.L; ++r) {
+            const int x = P.leaf_node[r];
+            same = kind[grp[x]] == nkind[ngrp[x]];
+        }
+        if (!same) {
+            grp = ngrp;
+            kind = nkind;
+            number();
+            continue;
+        }
+        // the words the accept bit reads
+        std::vector<V> upd(ns > 0 ? ns : 1, E.zero);
+        for (int r = 0; r < P.L; ++r) {
+            const int x = P.leaf_node[r];
+            if (slot[x] >= 0) upd[slot[x]] = in[x];
+        }
+        std::vector<char> live(ns > 0 ? ns : 1, 0);
+        std::vector<int> todo = out[0].c < 0 ? E.reads(out[0].n) : std::vector<int>{};
+        while (!todo.empty()) {
+            const int k = todo.back();
+            todo.pop_back();
+            if (live[k]) continue;
+            live[k] = 1;
+            if (upd[k].c < 0)
+                for (int j : E.reads(upd[k].n)) todo.push_back(j);
+        }
+        bool dropped = false;
+        for (int r = 0; r < P.L; ++r) {
+            const int x = P.leaf_node[r];
+            if (slot[x] >= 0 && !live[slot[x]]) {
+                kind[grp[x]] = kDead;
+                dropped = true;
+            }
+        }
+        if (dropped) {
+            number();
+            continue;
+        }
+        // commit the new state after every value is computed
+        std::ostringstream tail;
+        std::vector<char> done(ns > 0 ? ns : 1, 0);
+        for (int r = 0; r < P.L; ++r) {
+            const int x = P.leaf_node[r];
+            if (slot[x] < 0 || done[slot[x]]) continue;
+            done[slot[x]] = 1;
+            tail << "    s[" << slot[x] << "] = " << Emitter::str(in[x]) << ";\n";
+        }
+        tail << "    acc = " << Emitter::str(out[0]) << ";\n";
+        std::ostringstream src;
+        src << "#define RX_NS " << (ns > 0 ? ns : 1) << "\n";
+        src << "__device__ __forceinline__ void rx_step(u32 (&s)[RX_NS], u32& acc, u32 b0, u32 b1, u32 b2, u32 b3,"
+               " u32 b4, u32 b5, u32 b6, u32 b7) {\n";
+        src << E.code.str() << tail.str() << "}\n";
+        src << "__device__ __forceinline__ void rx_init(u32 (&s)[RX_NS], u32& acc) {\n";
+        for (int k = 0; k < (ns > 0 ? ns : 1); ++k) src << "    s[" << k << "] = 0u;\n";
+        std::fill(done.begin(), done.end(), 0);
+        for (int r = 0; r < P.L; ++r) {
+            const int x = P.leaf_node[r];
+            if (slot[x] >= 0 && !done[slot[x]] && is_first(r)) {
+                done[slot[x]] = 1;
+                src << "    s[" << slot[x] << "] = 0xffffffffu;\n";
+            }
+        }
+        src << "    acc = " << (P.nullable ? "0xffffffffu" : "0u") << ";\n}\n";
+        if (n_state) *n_state = ns;
+        if (n_ops) *n_ops = E.ops;
+        if (suffix_slot) {
+            const int suf = search_suffix_leaf(P);
+            *suffix_slot = suf >= 0 && slot[suf] >= 0 ? slot[suf] : -1;
+        }
+        return src.str();
     }
-    // commit the new state after every value is computed
-    std::ostringstream tail;
-    for (int r = 0; r < P.L; ++r) {
-        const int x = P.leaf_node[r];
-        if (slot[x] < 0) continue;
-        tail << "    s[" << slot[x] << "] = " << Emitter::str(in[x]) << ";\n";
-    }
-    tail << "    acc = " << Emitter::str(out[0]) << ";\n";
-    std::ostringstream src;
-    src << "#define RX_NS " << (ns > 0 ? ns : 1) << "\n";
-    src << "__device__ __forceinline__ void rx_step(u32 (&s)[RX_NS], u32& acc, u32 b0, u32 b1, u32 b2, u32 b3,"
-           " u32 b4, u32 b5, u32 b6, u32 b7) {\n";
-    src << E.code.str() << tail.str() << "}\n";
-    src << "__device__ __forceinline__ void rx_init(u32 (&s)[RX_NS], u32& acc) {\n";
-    for (int k = 0; k < (ns > 0 ? ns : 1); ++k) src << "    s[" << k << "] = 0u;\n";
-    for (int r = 0; r < P.L; ++r) {
-        const int x = P.leaf_node[r];
-        if (slot[x] >= 0 && ((P.first[r >> 5] >> (r & 31)) & 1)) src << "    s[" << slot[x] << "] = 0xffffffffu;\n";
-    }
-    src << "    acc = " << (P.nullable ? "0xffffffffu" : "0u") << ";\n}\n";
-    if (n_state) *n_state = ns;
-    if (n_ops) *n_ops = E.ops;
-    return src.str();
 }
 
 // 32x32 bit transpose: afterwards a[k] bit j == (before) a[j] bit k.  The two
@@ -897,33 +1015,26 @@ __device__ __forceinline__ void rx_planes_tick(u32 (&s)[PR::NS], u32& acc, u32& 
 const char* kPlanesKernelSource = R"RX(
 // ---- device kernel ----
 typedef unsigned int rx_pv4 __attribute__((ext_vector_type(4)));
-// Slab s (ticks slab_tick[s] .. slab_tick[s+1] of `planes`) for program PR;
-// lane l writes its 32 results (bit j: the slab's entry 64 j + l) to res[l].
+// Ticks [t0, t1) of a slab (p: the slab's planes at tick 0, this lane's
+// column) through program PR's circuit.  Each tick is rx_planes_tick's (four
+// steps, the accept bit kept where a string still has bytes), with its loads
+// spread through it: the registers of a position's planes are refilled with
+// the next tick's as soon as that position is done, so every load has a whole
+// tick to arrive and no second set of registers is needed.  The first tick's
+// values get a use of their own before the loop: the compiler then keeps the
+// loop's loads where they are instead of merging each with the first tick's
+// into one load at the top of the loop, next to its first use.
 template <class PR>
-__device__ __forceinline__ void rx_run_slab(const u32* __restrict__ planes, const long long* __restrict__ slab_tick,
-                                            long long s, u32* __restrict__ res) {
-    const int lane = threadIdx.x & 63;
-    const long long t0 = slab_tick[s], T = slab_tick[s + 1] - t0;
-    const rx_pv4* p = reinterpret_cast<const rx_pv4*>(planes) + t0 * (9 * 64) + lane;
-    u32 st[PR::NS];
-    u32 acc;
-    PR::init(st, acc);
-    u32 accf = acc;
-    // Each tick is rx_planes_tick's (four steps, the accept bit kept where a
-    // string still has bytes), with its loads spread through it: the
-    // registers of a position's planes are refilled with the next tick's as
-    // soon as that position is done, so every load has a whole tick to
-    // arrive and no second set of registers is needed.  The first tick's
-    // values get a use of their own before the loop: the compiler then keeps
-    // the loop's loads where they are instead of merging each with the first
-    // tick's into one load at the top of the loop, next to its first use.
+__device__ __forceinline__ void rx_ticks(const rx_pv4* p, long long t0, long long t1, u32 (&st)[PR::NS], u32& acc,
+                                         u32& accf) {
+    if (t0 >= t1) return;
     rx_pv4 cur[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) cur[q] = T > 0 ? p[q * 64] : rx_pv4{0u, 0u, 0u, 0u};
+    for (int q = 0; q < 9; ++q) cur[q] = p[t0 * (9 * 64) + q * 64];
 #pragma unroll
     for (int q = 0; q < 9; ++q) asm volatile("" ::"v"(cur[q]));
-    for (long long t = 0; t < T; ++t) {
-        const rx_pv4* pn = p + (t + 1 < T ? t + 1 : t) * (9 * 64);
+    for (long long t = t0; t < t1; ++t) {
+        const rx_pv4* pn = p + (t + 1 < t1 ? t + 1 : t) * (9 * 64);
         const u32 v[4] = {cur[8].x, cur[8].y, cur[8].z, cur[8].w};
         cur[8] = pn[8 * 64];
         __builtin_amdgcn_sched_barrier(0);
@@ -937,7 +1048,112 @@ __device__ __forceinline__ void rx_run_slab(const u32* __restrict__ planes, cons
             __builtin_amdgcn_sched_barrier(0);
         }
     }
+}
+
+// Slab s (ticks slab_tick[s] .. slab_tick[s+1] of `planes`) for program PR;
+// lane l writes its 32 results (bit j: the slab's entry 64 j + l) to res[l].
+template <class PR>
+__device__ __forceinline__ void rx_run_slab(const u32* __restrict__ planes, const long long* __restrict__ slab_tick,
+                                            long long s, u32* __restrict__ res) {
+    const int lane = threadIdx.x & 63;
+    const long long t0 = slab_tick[s], T = slab_tick[s + 1] - t0;
+    const rx_pv4* p = reinterpret_cast<const rx_pv4*>(planes) + t0 * (9 * 64) + lane;
+    u32 st[PR::NS];
+    u32 acc;
+    PR::init(st, acc);
+    u32 accf = acc;
+    rx_ticks<PR>(p, 0, T, st, acc, accf);
     res[lane] = accf;   // one coalesced word per lane
+}
+
+// A long slab of a searched program on two wavefronts.  The first runs the
+// slab from the start as usual; the second starts at the middle tick MT from
+// the start state and leaves copies of its state in LDS after 4, 8, 16, ...
+// of its ticks.  At each of those points the first compares its own state
+// with the copy: once they are equal for every string they stay equal (the
+// step depends on the state and the byte alone, Def. 5.1), so the first
+// stops there and every string that still has bytes takes the second's
+// accept bit.  Strings that have ended by then, and strings already in the
+// any-byte loop of the search suffix (they accept whatever follows), are left
+// out of the comparison.  A searched program's start state lies in every state it
+// reaches (the any-byte loop of its prefix leads back to it after every
+// byte), so the two meet as soon as the matches begun before the middle have
+// died or joined the ones begun after it -- usually within a few bytes.  The
+// first waits for a copy a bounded time; past that it runs on (same bits).
+// One call of the tick loop serves both wavefronts and every segment.
+template <class PR>
+__device__ __forceinline__ void rx_run_slab_spec(const u32* __restrict__ planes,
+                                                 const long long* __restrict__ slab_tick, long long s,
+                                                 u32* __restrict__ res, u32* lds) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const long long t0 = slab_tick[s], T = slab_tick[s + 1] - t0;
+    const rx_pv4* p = reinterpret_cast<const rx_pv4*>(planes) + t0 * (9 * 64) + lane;
+    volatile u32* flags = lds;       // copy c of the second wavefront is in place when flags[c] != 0
+    u32* accx = lds + 8;             // the second wavefront's accept bits, one word per lane
+    u32* ck = lds + 8 + 64;          // copy c, state word k, lane l at (c * NS + k) * 64 + l
+    constexpr int NS = PR::NS, NCP = PR::NCP;
+    const bool split = PR::SPEC && NCP > 0 && T >= 16;
+    if (threadIdx.x < 8) flags[threadIdx.x] = 0u;
+    __syncthreads();
+    // unsplit: the first wavefront runs the whole slab, the second nothing
+    const long long MT = split ? T / 2 : T;
+    const int ncp = split ? NCP : 0;
+    u32 st[NS];
+    u32 acc;
+    PR::init(st, acc);
+    u32 accf = wave == 0 ? acc : 0u;
+    long long t = wave == 0 ? 0 : MT;
+    bool same = false;
+    u32 vnext = 0u, sure = 0u;
+    // c: the copy due at the end of the next segment (-1: the first
+    // wavefront's first half, no copy)
+    int c = wave == 0 ? -1 : 0;
+#pragma clang loop unroll(disable)
+    for (;;) {
+        const long long tc = c < 0 ? MT : MT + (4ll << c);
+        const bool at_ck = c >= 0 && c < ncp && tc <= T;
+        const long long te = c < 0 ? MT : at_ck ? tc : T;
+        rx_ticks<PR>(p, t, te, st, acc, accf);
+        t = te;
+        if (c >= 0) {
+            if (!at_ck) break;
+            if (wave == 1) {
+#pragma unroll
+                for (int k = 0; k < NS; ++k) ck[(c * NS + k) * 64 + lane] = st[k];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                if (lane == 0) flags[c] = 1u;
+            } else {
+                int spin = 0;
+                while (flags[c] == 0u && spin < (1 << 22)) {
+                    __builtin_amdgcn_s_sleep(2);
+                    ++spin;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                if (flags[c] != 0u) {
+                    // only strings with bytes left count, and of those not the
+                    // ones already in the search suffix's any-byte loop (they
+                    // accept whatever follows)
+                    vnext = t < T ? p[t * (9 * 64) + 8 * 64].x : 0u;
+                    sure = PR::SUF >= 0 ? st[PR::SUF >= 0 ? PR::SUF : 0] : 0u;
+                    u32 diff = 0u;
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) diff |= st[k] ^ ck[(c * NS + k) * 64 + lane];
+                    same = __builtin_amdgcn_ballot_w64((diff & vnext & ~sure) != 0u) == 0ull;
+                }
+                if (same) break;
+            }
+        }
+        ++c;
+    }
+    if (wave == 1) accx[lane] = accf;
+    __syncthreads();
+    if (wave == 0) {
+        // strings that go on past the meeting point take the second
+        // wavefront's bit, or accept if they are in the suffix loop
+        const u32 go_on = same ? vnext : 0u;
+        res[lane] = (accf & ~go_on) | ((accx[lane] | sure) & go_on);
+    }
 }
 
 // One wavefront per (program, slab) for the slabs of rank r_lo <= r < r_hi
@@ -959,24 +1175,52 @@ extern "C" __global__ __launch_bounds__(64) void rx_planes_multi(const u32* __re
     if (r < 16) __builtin_amdgcn_s_setprio(3);
     rx_dispatch(p, planes, slab_tick, S - 1 - r, res + (p * max_slabs + (S - 1 - r)) * 64);
 }
+
+// The same slabs with two wavefronts per (program, slab): a searched
+// program's slab of 16 ticks or more gets a second wavefront that starts in
+// the middle (rx_run_slab_spec); otherwise the first wavefront runs it whole.  Dynamic LDS: RX_SPEC_LDS
+// bytes (flags, B's accept bits, the checkpoints).
+extern "C" __global__ __launch_bounds__(128) void rx_planes_spec(const u32* __restrict__ planes,
+        const long long* __restrict__ slab_tick, const long long* __restrict__ info, u32* __restrict__ res,
+        long long max_slabs, long long r_lo, long long r_hi) {
+    extern __shared__ u32 rx_spec_lds[];
+    const long long b = blockIdx.x;
+    const long long k = b >> 3;
+    const int p = (int)(k % RX_NPROGS);
+    const long long r = r_lo + (k / RX_NPROGS) * 8 + (b & 7);
+    const long long n_sliced = info[0];
+    const long long S = (n_sliced + 2047) / 2048;
+    if (r >= S || r >= r_hi) return;
+    __builtin_amdgcn_s_setprio(3);
+    rx_dispatch_spec(p, planes, slab_tick, S - 1 - r, res + (p * max_slabs + (S - 1 - r)) * 64, rx_spec_lds);
+}
 )RX";
 
 // The plane-form source for a list of programs: program k's circuit as
 // struct RxProgk (its step and start state in namespace rxqk), the tick
 // template, a dispatch over the programs and the kernel.
-std::string jit_multi_planes_source(const Program* const* progs, int n, int* max_state) {
+std::string jit_multi_planes_source(const Program* const* progs, int n, int* max_state, int* spec_lds) {
     std::ostringstream s;
     s << "typedef unsigned int u32;\n#define RX_NPROGS " << n << "\n";
     int mx = 0;
+    int64_t ck_words = 0;   // the largest checkpoint area of a split slab
     for (int k = 0; k < n; ++k) {
-        int ns = 0;
-        std::string step = jit_step_source(*progs[k], &ns, nullptr);
+        int ns = 0, suf = -1;
+        std::string step = jit_step_source(*progs[k], &ns, nullptr, &suf);
         if (ns < 1) ns = 1;
         mx = std::max(mx, ns);
+        // a searched program's long slabs may be split in two; as many
+        // checkpoints (after 4, 8, 16, ... ticks) as the LDS budget holds
+        const bool spec = search_prefix_leaf(*progs[k]) >= 0;
+        int ncp = spec ? (int)std::min<int64_t>(kSpecCheckpoints, kSpecLdsBudget / (4 * 64 * (int64_t)ns)) : 0;
+        ck_words = std::max<int64_t>(ck_words, (int64_t)ncp * ns * 64);
         // the step source opens with its own #define of RX_NS
         const size_t eol = step.find('\n');
         s << "#define RX_NS " << ns << "\nnamespace rxq" << k << " {\n" << step.substr(eol + 1) << "}\n#undef RX_NS\n";
         s << "struct RxProg" << k << " {\n    static constexpr int NS = " << ns << ";\n"
+          << "    static constexpr bool SPEC = " << (spec ? "true" : "false") << ";\n"
+          << "    static constexpr int NCP = " << ncp << ";\n"
+          << "    static constexpr int SUF = " << suf << ";\n"
           << "    __device__ static __forceinline__ void init(u32 (&s)[NS], u32& acc) { rxq" << k << "::rx_init(s, acc); }\n"
           << "    __device__ static __forceinline__ void step(u32 (&s)[NS], u32& acc, u32 b0, u32 b1, u32 b2, u32 b3, "
              "u32 b4, u32 b5, u32 b6, u32 b7) {\n        rxq" << k << "::rx_step(s, acc, b0, b1, b2, b3, b4, b5, b6, b7);\n    }\n};\n";
@@ -993,10 +1237,16 @@ std::string jit_multi_planes_source(const Program* const* progs, int n, int* max
     for (int k = 0; k < n; ++k)
         disp << "    case " << k << ": rx_run_slab<RxProg" << k << ">(planes, slab_tick, s, res); break;\n";
     disp << "    default: break;\n    }\n}\n";
+    disp << "__device__ __forceinline__ void rx_dispatch_spec(int p, const u32* __restrict__ planes, const long long* "
+            "__restrict__ slab_tick, long long s, u32* __restrict__ res, u32* lds) {\n    switch (p) {\n";
+    for (int k = 0; k < n; ++k)
+        disp << "    case " << k << ": rx_run_slab_spec<RxProg" << k << ">(planes, slab_tick, s, res, lds); break;\n";
+    disp << "    default: break;\n    }\n}\n";
     disp << kern.substr(kern.find("extern \"C\""));
     (void)at;
     s << disp.str();
     if (max_state) *max_state = mx;
+    if (spec_lds) *spec_lds = (int)(4 * (8 + 64 + ck_words));
     return s.str();
 }
 
@@ -1005,6 +1255,8 @@ std::string jit_multi_planes_source(const Program* const* progs, int n, int* max
 struct PlaneModule {
     hipModule_t mod = nullptr;
     hipFunction_t fn = nullptr;
+    hipFunction_t fn_spec = nullptr;   // two wavefronts per (program, slab), long slabs split in two
+    int spec_lds = 0;                  // its dynamic LDS bytes
     int scratch = 0;
 };
 namespace {
@@ -1115,7 +1367,7 @@ int jit_code(const std::string& src, const std::string& arch, std::vector<char>*
 
 std::string jit_planes_source(const Program& P, int* n_state) {
     const Program* one[1] = {&P};
-    return jit_multi_planes_source(one, 1, n_state);
+    return jit_multi_planes_source(one, 1, n_state, nullptr);
 }
 
 namespace {
@@ -1129,8 +1381,8 @@ std::string plane_key(int dev, const Program* const* progs, int n) {
 }  // namespace
 
 int jit_prepare_planes(const Program* const* progs, int n, const char* arch_in, int* spill_bytes) {
-    int mx = 0;
-    const std::string src = jit_multi_planes_source(progs, n, &mx);
+    int mx = 0, spec_lds = 0;
+    const std::string src = jit_multi_planes_source(progs, n, &mx, &spec_lds);
     if (mx > kJitPlanesMaxState)
         return fail(RX_ETOOBIG, "the plane-form circuit keeps at most " + std::to_string(kJitPlanesMaxState) +
                                     " state words; a program needs " + std::to_string(mx));
@@ -1151,6 +1403,8 @@ int jit_prepare_planes(const Program* const* progs, int n, const char* arch_in, 
     PlaneModule* K = new PlaneModule;
     hipError_t e = hipModuleLoadData(&K->mod, code.data());
     if (e == hipSuccess) e = hipModuleGetFunction(&K->fn, K->mod, "rx_planes_multi");
+    if (e == hipSuccess) e = hipModuleGetFunction(&K->fn_spec, K->mod, "rx_planes_spec");
+    K->spec_lds = spec_lds;
     if (e == hipSuccess) e = hipFuncGetAttribute(&K->scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, K->fn);
     if (e != hipSuccess) {
         if (K->mod) hipModuleUnload(K->mod);
@@ -1176,7 +1430,7 @@ bool jit_planes_prepared(const Program* const* progs, int n) {
 
 int launch_planes_circuits(const Program* const* progs, int n, const uint32_t* planes, const int64_t* slab_tick,
                            const int64_t* info, uint32_t* res, int64_t max_slabs, int64_t r_lo, int64_t r_hi,
-                           void* stream) {
+                           bool split, void* stream) {
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return (int)hipErrorInvalidDevice;
     PlaneModule* K = nullptr;
@@ -1196,6 +1450,9 @@ int launch_planes_circuits(const Program* const* progs, int n, const uint32_t* p
     void* a3 = res;
     long long a4 = max_slabs, a5 = r_lo, a6 = hi;
     void* args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6};
+    if (split)
+        return (int)hipModuleLaunchKernel(K->fn_spec, grid, 1, 1, 128, 1, 1, (unsigned)K->spec_lds, (hipStream_t)stream,
+                                          args, nullptr);
     return (int)hipModuleLaunchKernel(K->fn, grid, 1, 1, 64, 1, 1, 0, (hipStream_t)stream, args, nullptr);
 }
 

@@ -705,7 +705,8 @@ int launch_planes_multi(const PlaneMultiArgs& m) {
     if (hipError_t e = hipGetLastError()) return (int)e;
     if (hipError_t e = hipEventRecord(side->fork, st)) return (int)e;
     if (hipError_t e = hipStreamWaitEvent(side->stream, side->fork, 0)) return (int)e;
-    if (int e = launch_planes_circuits(m.progs, m.n_progs, planes, a.slab_tick, a.info, res, S, 0, R, side->stream))
+    if (int e = launch_planes_circuits(m.progs, m.n_progs, planes, a.slab_tick, a.info, res, S, 0, R, true,
+                                       side->stream))
         return e;
     if (hipError_t e = hipEventRecord(side->join, side->stream)) return (int)e;
     pa.r_lo = R;
@@ -713,7 +714,7 @@ int launch_planes_multi(const PlaneMultiArgs& m) {
     if (S > R)
         hipLaunchKernelGGL(k_planes<false>, dim3((unsigned)(a.tick_cap / kGroupTicks + S + 1)), dim3(256), 0, st, pa);
     if (hipError_t e = hipGetLastError()) return (int)e;
-    if (int e = launch_planes_circuits(m.progs, m.n_progs, planes, a.slab_tick, a.info, res, S, R, S, m.stream))
+    if (int e = launch_planes_circuits(m.progs, m.n_progs, planes, a.slab_tick, a.info, res, S, R, S, false, m.stream))
         return e;
     GatherArgs ga;
     ga.rank = a.rank;

@@ -293,9 +293,16 @@ def test_sliced_pathological(dev):
         assert want[:32].sum() == 0 and want[32:].all()
         for burst in (3, 4, 5):
             assert np.array_equal(fixed_match(p, s, 1008, dev, rx.VARIANT_SLICED, burst), want), family
-    big = W.pathological_program("altstar", 585)
+    # the 4,096-node programs: every 'a' leaf of one family holds the same word, so the circuit is tiny
+    for family, k in (("nested", 819), ("altstar", 585)):
+        prog = W.pathological_program(family, k)
+        s = W.pathological_strings(family, 1008, count=64)
+        p = rx.compile(prog.ast, prog.root).upload(dev).jit()
+        assert p.jit_stats()["state_words"] <= 2
+        assert np.array_equal(fixed_match(p, s, 1008, dev, rx.VARIANT_SLICED, 4), oracle_match(prog, s)), family
+    # a 200-byte anchored literal: 200 distinct words, more than the circuit keeps
     with pytest.raises(rx.RxError) as ei:
-        rx.compile(big.ast, big.root).jit()
+        rx.compile_regex(b"ab" * 100, search=False).jit()
     assert ei.value.code == rx.RX_ETOOBIG
 
 

@@ -149,3 +149,48 @@ def test_hiprtc_compiles_for_gfx950():
     t0 = time.perf_counter()
     rx.compile(prog.ast, prog.root, prog.classes, True).jit("gfx950")
     assert time.perf_counter() - t0 < 0.5
+
+
+def _state_words(p):
+    return int(p.jit_source().split("#define RX_NS ", 1)[1].split()[0])
+
+
+@pytest.mark.parametrize("pattern,search,words,member", [
+    (b"abc", False, 3, b"abc"),              # anchored literal: one word per byte, none shared
+    (b"(x|y|z)*w", False, 1, b"xyzzyxw"),    # every leaf live at the start and with the same update
+    (b"a*b", True, 1, b"zzaaabzz"),          # searched: a and b always live (constants), the suffix loop is the word
+    (b"(ab)*c", True, 1, b"xabababcx"),      # searched: b only feeds updates that are always live, so it is dropped
+    (b"(ab)*c", False, 2, b"ababc"),         # anchored: a and c share a word (same start, same update), b has its own
+])
+def test_state_words_closed_forms(pattern, search, words, member):
+    """State words of the bit-sliced circuit, counted by hand from the position automaton (Def. 5.1):
+    leaves with equal start values and updates share a word, constant leaves and leaves the accept
+    bit never reads have none; the circuit still gives the oracle's bits (random strings over the
+    pattern's letters, every seventh one a member)."""
+    p = rx.compile_regex(pattern, search=search)
+    assert _state_words(p) == words
+    ast, root, classes = rx.parse(pattern)
+    rng = np.random.default_rng(len(pattern) + search)
+    n, length = 3000, len(member)
+    s = fixed_strings(rng, n, length, b"abcxyzw")
+    s.data.reshape(n, length)[::7] = np.frombuffer(member, np.uint8)
+    want = oracle.match(ast, root, classes, search, s.data, s.offsets)
+    assert want[::7].all() and not want.all()
+    assert np.array_equal(cpu_circuit(p)(s.data, length, s.n), want)
+
+
+def test_state_words_pathological_and_limit():
+    """The 4,096-node pathological programs need at most two words (all their 'a' leaves agree); a
+    200-byte anchored literal needs 200, more than the circuit keeps, and is refused."""
+    for family, k in (("nested", 819), ("altstar", 585)):
+        prog = W.pathological_program(family, k)
+        p = rx.compile(prog.ast, prog.root)
+        assert _state_words(p) <= 2
+        s = W.pathological_strings(family, 48, count=64)
+        want = oracle.match(prog.ast, prog.root, prog.classes, False, s.data, s.offsets)
+        assert np.array_equal(cpu_circuit(p)(s.data, 48, s.n), want)
+    p = rx.compile_regex(b"ab" * 100, search=False)
+    assert _state_words(p) == 200
+    with pytest.raises(rx.RxError) as ei:
+        p.jit("gfx950")
+    assert ei.value.code == rx.RX_ETOOBIG

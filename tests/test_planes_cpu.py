@@ -231,3 +231,170 @@ def test_plane_circuit_small_anchored_programs(seed):
     got = planes_circuit(p)(s)
     want = oracle.match(prog.ast, prog.root, prog.classes, False, s.data, s.offsets, threads=4)
     assert np.array_equal(got, want)
+
+
+SPEC_DRIVER = r"""
+#include "rx_planes.h"
+#include <vector>
+// The split run of a long slab (the device kernel's two wavefronts), one lane
+// at a time: the second runs from the start state over the second half and
+// keeps its state after 4, 8, ... ticks; the first runs from the start and, at
+// each of those ticks, stops if its state equals the kept one for every string
+// of every lane (the device's ballot) that has bytes left and is not in the
+// search suffix's loop; strings with bytes left then take the second's accept
+// bit, or accept if in that loop.
+extern "C" int run_planes_spec(const uint8_t* bytes, const int64_t* lo, const int64_t* len, int64_t n,
+                               unsigned char* out, int64_t* stopped) {
+    const int NS = RxProg0::NS, NCP = RxProg0::NCP;
+    *stopped = 0;
+    for (int64_t s0 = 0; s0 < n; s0 += 2048) {
+        const int64_t count = n - s0 < 2048 ? n - s0 : 2048;
+        int64_t mx = 0;
+        for (int64_t k = 0; k < count; ++k) if (len[s0 + k] > mx) mx = len[s0 + k];
+        const int64_t T = (mx + 3) / 4;
+        // every tick of every lane
+        std::vector<u32> W((size_t)(T > 0 ? T : 1) * 64 * 36);
+        for (int lane = 0; lane < 64; ++lane)
+            for (int64_t c = 0; 4 * c < T; ++c) {
+                uint32_t win[32][4];
+                int64_t L[32];
+                for (int j = 0; j < 32; ++j) {
+                    const int64_t k = j * 64 + lane;
+                    const int64_t o = k < count ? lo[s0 + k] : 0, m = k < count ? len[s0 + k] : 0;
+                    L[j] = m;
+                    rx::planes_window16(bytes + o, m, 16 * c, win[j]);
+                }
+                for (int kk = 0; kk < 4 && 4 * c + kk < T; ++kk) {
+                    uint32_t w[36];
+                    rx::planes_tick(win, L, kk, 4 * (4 * c + kk), 0, w);
+                    for (int i = 0; i < 36; ++i) W[((size_t)(4 * c + kk) * 64 + lane) * 36 + i] = w[i];
+                }
+            }
+        auto tick = [&](int lane, int64_t t, u32 (&st)[RxProg0::NS], u32& acc, u32& accf) {
+            const u32* w = &W[((size_t)t * 64 + lane) * 36];
+            u32 ww[36];
+            for (int i = 0; i < 36; ++i) ww[i] = w[i];
+            rx_planes_tick<RxProg0>(st, acc, accf, ww);
+        };
+        const bool split = RxProg0::SPEC && NCP > 0 && T >= 16;
+        std::vector<u32> res(64);
+        if (!split) {
+            for (int lane = 0; lane < 64; ++lane) {
+                u32 st[RxProg0::NS], acc;
+                RxProg0::init(st, acc);
+                u32 accf = acc;
+                for (int64_t t = 0; t < T; ++t) tick(lane, t, st, acc, accf);
+                res[lane] = accf;
+            }
+        } else {
+            const int64_t MT = T / 2;
+            // the second wavefront: kept states of every lane
+            std::vector<u32> ck((size_t)NCP * NS * 64), accx(64);
+            for (int lane = 0; lane < 64; ++lane) {
+                u32 st[RxProg0::NS], acc;
+                RxProg0::init(st, acc);
+                u32 accf = 0;
+                int c = 0;
+                for (int64_t t = MT; t < T; ++t) {
+                    tick(lane, t, st, acc, accf);
+                    if (c < NCP && t + 1 - MT == (4ll << c)) {
+                        for (int k = 0; k < NS; ++k) ck[((size_t)c * NS + k) * 64 + lane] = st[k];
+                        ++c;
+                    }
+                }
+                accx[lane] = accf;
+            }
+            // the first, in lockstep over the lanes (its exit needs every lane equal)
+            std::vector<u32> S((size_t)64 * NS), acc(64), accf(64);
+            for (int lane = 0; lane < 64; ++lane) {
+                u32 st[RxProg0::NS];
+                RxProg0::init(st, acc[lane]);
+                accf[lane] = acc[lane];
+                for (int k = 0; k < NS; ++k) S[(size_t)lane * NS + k] = st[k];
+            }
+            bool same = false;
+            int c = 0;
+            int64_t t = 0;
+            u32 vn[64] = {0}, sr[64] = {0};
+            for (; t < T && !same; ++t) {
+                for (int lane = 0; lane < 64; ++lane) {
+                    u32 st[RxProg0::NS];
+                    for (int k = 0; k < NS; ++k) st[k] = S[(size_t)lane * NS + k];
+                    tick(lane, t, st, acc[lane], accf[lane]);
+                    for (int k = 0; k < NS; ++k) S[(size_t)lane * NS + k] = st[k];
+                }
+                if (t + 1 > MT && c < NCP && t + 1 - MT == (4ll << c)) {
+                    // strings with bytes left, not yet in the suffix loop
+                    bool all = true;
+                    for (int lane = 0; lane < 64; ++lane) {
+                        const u32 live = t + 1 < T ? W[((size_t)(t + 1) * 64 + lane) * 36 + 32] : 0u;
+                        const u32 sure = RxProg0::SUF >= 0 ? S[(size_t)lane * NS + (RxProg0::SUF >= 0 ? RxProg0::SUF : 0)] : 0u;
+                        for (int k = 0; k < NS; ++k)
+                            if ((S[(size_t)lane * NS + k] ^ ck[((size_t)c * NS + k) * 64 + lane]) & live & ~sure)
+                                all = false;
+                    }
+                    if (all) {
+                        same = true;
+                        ++*stopped;
+                        for (int lane = 0; lane < 64; ++lane) {
+                            vn[lane] = t + 1 < T ? W[((size_t)(t + 1) * 64 + lane) * 36 + 32] : 0u;
+                            sr[lane] = RxProg0::SUF >= 0 ? S[(size_t)lane * NS + (RxProg0::SUF >= 0 ? RxProg0::SUF : 0)] : 0u;
+                        }
+                    }
+                    ++c;
+                }
+            }
+            for (int lane = 0; lane < 64; ++lane) {
+                const u32 go_on = same ? vn[lane] : 0u;
+                res[lane] = (accf[lane] & ~go_on) | ((accx[lane] | sr[lane]) & go_on);
+            }
+        }
+        for (int lane = 0; lane < 64; ++lane)
+            for (int j = 0; j < 32; ++j) {
+                const int64_t k = j * 64 + lane;
+                if (k < count) out[s0 + k] = (unsigned char)((res[lane] >> j) & 1u);
+            }
+    }
+    return 1;
+}
+"""
+
+
+def spec_circuit(p):
+    src = p.jit_planes_source()
+    host_part = src.split("// ---- device kernel ----")[0]
+    code = ("#define __device__\n#define __forceinline__ inline\n" + PERM_CPU + host_part + HOST_PRIMS + SPEC_DRIVER)
+    lib = _build(code, "spec")
+    lib.run_planes_spec.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+
+    def run(s):
+        lo = np.ascontiguousarray(s.offsets[:-1], np.int64)
+        ln = np.ascontiguousarray(np.diff(s.offsets), np.int64)
+        data = s.data if s.data.size else np.zeros(16, np.uint8)
+        out = np.zeros(max(s.n, 1), np.uint8)
+        stopped = ctypes.c_int64()
+        lib.run_planes_spec(data.ctypes.data, lo.ctypes.data, ln.ctypes.data, s.n, out.ctypes.data,
+                            ctypes.byref(stopped))
+        return out[:s.n], stopped.value
+
+    return run, src
+
+
+@pytest.mark.parametrize("k", [3, 5, 12, 15])
+def test_split_long_slab_against_oracle(k):
+    """A long slab of a searched program on two runs (a second from the start state over the second half,
+    the first stopping where its state equals the second's at a kept tick) gives the oracle's bits;
+    lines of 100-700 bytes of the batched workload's kind."""
+    prog = W.multi_programs(seed=2)[k]
+    p = rx.compile(prog.ast, prog.root, prog.classes, True)
+    run, src = spec_circuit(p)
+    assert "SPEC = true" in src
+    s = W.multi_lines(seed=30 + k, n=2048 * 3, hi=700)
+    lens = np.diff(s.offsets)
+    keep = np.nonzero(lens >= 100)[0][:4096]
+    s = W.pack([bytes(s.data[s.offsets[i]:s.offsets[i + 1]]) for i in keep])
+    got, stopped = run(s)
+    want = oracle.match(prog.ast, prog.root, prog.classes, True, s.data, s.offsets, threads=8)
+    print(f"program {k}: {stopped} of {(s.n + 2047) // 2048} slabs met the second run early; "
+          f"accepted {int(want.sum())}", flush=True)
+    assert np.array_equal(got, want)
