@@ -1051,7 +1051,8 @@ __device__ __forceinline__ void rx_ticks(const rx_pv4* p, long long t0, long lon
 }
 
 // Slab s (ticks slab_tick[s] .. slab_tick[s+1] of `planes`) for program PR;
-// lane l writes its 32 results (bit j: the slab's entry 64 j + l) to res[l].
+// lane l writes its 32 results (bit j: the slab's entry 64 j + l) to
+// res[l * RX_NPROGS] (the programs' words of one lane side by side).
 template <class PR>
 __device__ __forceinline__ void rx_run_slab(const u32* __restrict__ planes, const long long* __restrict__ slab_tick,
                                             long long s, u32* __restrict__ res) {
@@ -1063,7 +1064,7 @@ __device__ __forceinline__ void rx_run_slab(const u32* __restrict__ planes, cons
     PR::init(st, acc);
     u32 accf = acc;
     rx_ticks<PR>(p, 0, T, st, acc, accf);
-    res[lane] = accf;   // one coalesced word per lane
+    res[lane * RX_NPROGS] = accf;
 }
 
 // A long slab of a searched program on two wavefronts.  The first runs the
@@ -1152,7 +1153,7 @@ __device__ __forceinline__ void rx_run_slab_spec(const u32* __restrict__ planes,
         // strings that go on past the meeting point take the second
         // wavefront's bit, or accept if they are in the suffix loop
         const u32 go_on = same ? vnext : 0u;
-        res[lane] = (accf & ~go_on) | ((accx[lane] | sure) & go_on);
+        res[lane * RX_NPROGS] = (accf & ~go_on) | ((accx[lane] | sure) & go_on);
     }
 }
 
@@ -1160,7 +1161,7 @@ __device__ __forceinline__ void rx_run_slab_spec(const u32* __restrict__ planes,
 // (rank 0 = the longest slab).  Workgroup b runs on XCD b mod 8; its slab
 // rank is r_lo + 8 * ((b / 8) / n_progs) + b mod 8 and its program (b / 8)
 // mod n_progs.  info[0] = strings in slabs; the results of program p and
-// slab s go to res[(p * max_slabs + s) * 64 .. + 64).
+// slab s, lane l go to res[(s * 64 + l) * RX_NPROGS + p].
 extern "C" __global__ __launch_bounds__(64) void rx_planes_multi(const u32* __restrict__ planes,
         const long long* __restrict__ slab_tick, const long long* __restrict__ info, u32* __restrict__ res,
         long long max_slabs, long long r_lo, long long r_hi) {
@@ -1173,7 +1174,7 @@ extern "C" __global__ __launch_bounds__(64) void rx_planes_multi(const u32* __re
     if (r >= S || r >= r_hi) return;
     // the longest slabs set the kernel's length: their wavefronts issue first on their SIMDs
     if (r < 16) __builtin_amdgcn_s_setprio(3);
-    rx_dispatch(p, planes, slab_tick, S - 1 - r, res + (p * max_slabs + (S - 1 - r)) * 64);
+    rx_dispatch(p, planes, slab_tick, S - 1 - r, res + (S - 1 - r) * 64 * RX_NPROGS + p);
 }
 
 // The same slabs with two wavefronts per (program, slab): a searched
@@ -1192,7 +1193,7 @@ extern "C" __global__ __launch_bounds__(128) void rx_planes_spec(const u32* __re
     const long long S = (n_sliced + 2047) / 2048;
     if (r >= S || r >= r_hi) return;
     __builtin_amdgcn_s_setprio(3);
-    rx_dispatch_spec(p, planes, slab_tick, S - 1 - r, res + (p * max_slabs + (S - 1 - r)) * 64, rx_spec_lds);
+    rx_dispatch_spec(p, planes, slab_tick, S - 1 - r, res + (S - 1 - r) * 64 * RX_NPROGS + p, rx_spec_lds);
 }
 )RX";
 

@@ -517,8 +517,9 @@ struct GatherArgs {
     const int32_t* rank;
     const int32_t* sorted;
     const int64_t* info;
-    const uint32_t* res;
-    int64_t max_slabs, n, long_slabs;
+    const uint32_t* res;   // slab s, lane l, program p at (s * 64 + l) * n_progs + p
+    int64_t n, long_slabs;
+    int32_t n_progs;
     uint8_t* out;
 };
 
@@ -528,33 +529,45 @@ __device__ __forceinline__ int64_t long_cut(const GatherArgs& a, int64_t n_slice
     return S > a.long_slabs ? (S - a.long_slabs) * kSlabStrings : 0;
 }
 
+// The bit of sorted position r for every program, written to string i: the
+// programs' words of r's (slab, lane) are side by side, so one string reads
+// them as a few 16-byte loads, and each program's bytes go out in string
+// order.
+__device__ __forceinline__ void gather_one(const GatherArgs& a, int64_t r, int64_t i) {
+    const int P = a.n_progs;
+    const uint32_t* w = a.res + ((r >> 11) * 64 + (r & 63)) * P;
+    const int bit = (int)((r & (kSlabStrings - 1)) >> 6);
+    uint8_t* out = a.out + i;
+    int p = 0;
+    if ((P & 3) == 0) {
+        for (; p < P; p += 4) {
+            const uint4 v = *reinterpret_cast<const uint4*>(w + p);
+            out[(p + 0) * a.n] = (uint8_t)((v.x >> bit) & 1u);
+            out[(p + 1) * a.n] = (uint8_t)((v.y >> bit) & 1u);
+            out[(p + 2) * a.n] = (uint8_t)((v.z >> bit) & 1u);
+            out[(p + 3) * a.n] = (uint8_t)((v.w >> bit) & 1u);
+        }
+    }
+    for (; p < P; ++p) out[p * a.n] = (uint8_t)((w[p] >> bit) & 1u);
+}
+
 __global__ __launch_bounds__(256) void k_gather_out(GatherArgs a) {
     const int64_t n_sliced = a.info[0];
     const int64_t cut = long_cut(a, n_sliced);
-    const int64_t p = blockIdx.y;
-    const uint32_t* res = a.res + p * a.max_slabs * 64;
-    uint8_t* out = a.out + p * a.n;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = a.rank[i];
-        if (r >= cut) continue;
-        const int64_t k = r & (kSlabStrings - 1);
-        out[i] = (uint8_t)((res[(r >> 11) * 64 + (k & 63)] >> (k >> 6)) & 1u);
+        if (r < cut) gather_one(a, r, i);
     }
 }
 
-// The long slabs' results: one thread per sorted position e of those slabs
-// and program, written to string sorted[e].
+// The long slabs' results: one thread per sorted position e of those slabs,
+// written to string sorted[e].
 __global__ __launch_bounds__(256) void k_gather_long(GatherArgs a) {
     const int64_t n_sliced = a.info[0];
     const int64_t cut = long_cut(a, n_sliced);
-    const int64_t p = blockIdx.y;
-    const uint32_t* res = a.res + p * a.max_slabs * 64;
-    uint8_t* out = a.out + p * a.n;
     for (int64_t e = cut + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_sliced;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = e & (kSlabStrings - 1);
-        out[a.sorted[e]] = (uint8_t)((res[(e >> 11) * 64 + (k & 63)] >> (k >> 6)) & 1u);
-    }
+         e += (int64_t)gridDim.x * blockDim.x)
+        gather_one(a, e, a.sorted[e]);
 }
 
 // Work items for the strings too long for slabs: every program, 256 of them
@@ -721,16 +734,15 @@ int launch_planes_multi(const PlaneMultiArgs& m) {
     ga.sorted = a.sorted;
     ga.info = a.info;
     ga.res = res;
-    ga.max_slabs = S;
     ga.n = m.n;
     ga.long_slabs = R;
+    ga.n_progs = m.n_progs;
     ga.out = m.out;
-    const unsigned gx = (unsigned)((m.n + 255) / 256 < 2048 ? (m.n + 255) / 256 : 2048);
-    hipLaunchKernelGGL(k_gather_out, dim3(gx, (unsigned)m.n_progs), dim3(256), 0, st, ga);
+    const unsigned gx = (unsigned)((m.n + 255) / 256 < 8192 ? (m.n + 255) / 256 : 8192);
+    hipLaunchKernelGGL(k_gather_out, dim3(gx), dim3(256), 0, st, ga);
     // then the long slabs, once their circuits are done
     if (hipError_t e = hipStreamWaitEvent(st, side->join, 0)) return (int)e;
-    hipLaunchKernelGGL(k_gather_long, dim3((unsigned)((R * kSlabStrings + 255) / 256), (unsigned)m.n_progs), dim3(256), 0,
-                       st, ga);
+    hipLaunchKernelGGL(k_gather_long, dim3((unsigned)((R * kSlabStrings + 255) / 256)), dim3(256), 0, st, ga);
     // strings too long for a slab: table form, every program
     OverArgs o;
     o.info = a.info;
