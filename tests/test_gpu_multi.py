@@ -89,6 +89,24 @@ def test_planes_match_oracle(dev, multi_case):
     assert np.array_equal(got, want)
 
 
+def test_planes_many_slabs_match_oracle(dev):
+    """More slabs than the longest few that run first: the rest go through planes and circuits in parts
+    of about equal ticks (the planes of one part made while the circuits of the one before run); every
+    (program, line) bit equals the oracle's, over 98 slabs of log-normal lengths."""
+    from paper_1108_3126_amd import rx
+
+    progs = W.multi_programs(seed=2, count=6, lo=16, hi=300)
+    s = W.multi_lines(seed=7, n=200_000, hi=2000)
+    want = np.stack([oracle.match(p.ast, p.root, p.classes, p.search, s.data, s.offsets, threads=8) for p in progs])
+    ps = [rx.compile(p.ast, p.root, p.classes, p.search).upload(dev) for p in progs]
+    cfg = _planes(rx, ps)
+    d, o = torch.from_numpy(s.data).to(dev), torch.from_numpy(s.offsets).to(dev)
+    for _ in range(2):
+        got = rx.match_multi(ps, d, o, config=cfg).cpu().numpy()
+        bad = np.nonzero(got != want)
+        assert bad[0].size == 0, list(zip(bad[0][:5], bad[1][:5]))
+
+
 def test_planes_edge_cases(dev):
     """Empty strings, one-byte strings, lengths around the slab and sort limits (8190 sorts, 8191 and
     longer run in table form), a partial last slab, unaligned offsets, anchored and searched."""
