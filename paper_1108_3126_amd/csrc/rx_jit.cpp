@@ -1067,21 +1067,25 @@ __device__ __forceinline__ void rx_run_slab(const u32* __restrict__ planes, cons
     res[lane * RX_NPROGS] = accf;
 }
 
-// A long slab of a searched program on two wavefronts.  The first runs the
-// slab from the start as usual; the second starts at the middle tick MT from
-// the start state and leaves copies of its state in LDS after 4, 8, 16, ...
-// of its ticks.  At each of those points the first compares its own state
-// with the copy: once they are equal for every string they stay equal (the
-// step depends on the state and the byte alone, Def. 5.1), so the first
-// stops there and every string that still has bytes takes the second's
-// accept bit.  Strings that have ended by then, and strings already in the
-// any-byte loop of the search suffix (they accept whatever follows), are left
-// out of the comparison.  A searched program's start state lies in every state it
-// reaches (the any-byte loop of its prefix leads back to it after every
-// byte), so the two meet as soon as the matches begun before the middle have
-// died or joined the ones begun after it -- usually within a few bytes.  The
-// first waits for a copy a bounded time; past that it runs on (same bits).
-// One call of the tick loop serves both wavefronts and every segment.
+// A long slab of a searched program on up to RX_SPEC_WAVES wavefronts.  The
+// slab's T ticks are cut into ws segments of at least 64 ticks; wavefront i
+// starts at tick i * T / ws, the first from the start as usual, the others
+// from the start state, and each of those leaves copies of its state in LDS
+// after 4, 8, 16, 32 of its ticks.  Wavefront i runs on past its segment and,
+// at each of the next one's copies, compares its state with the copy: once
+// they are equal for every string they stay equal (the step depends on the
+// state and the byte alone, Def. 5.1), so it stops there, and from that tick
+// on the next wavefront holds the true state.  Strings that have ended by
+// then, and strings already in the any-byte loop of the search suffix (they
+// accept whatever follows), are left out of the comparison.  A searched
+// program's start state lies in every state it reaches (the any-byte loop of
+// its prefix leads back to it after every byte), so two neighbours meet as
+// soon as the matches begun before the later one's start have died or joined
+// those begun after it -- usually at the first copy.  Each string then takes
+// the accept bit of the wavefront that holds the true state at its last
+// byte.  A wavefront waits for a copy a bounded time; past that it runs on to
+// the end, with the same bits.  One call of the tick loop serves every
+// wavefront and every segment.
 template <class PR>
 __device__ __forceinline__ void rx_run_slab_spec(const u32* __restrict__ planes,
                                                  const long long* __restrict__ slab_tick, long long s,
@@ -1090,70 +1094,91 @@ __device__ __forceinline__ void rx_run_slab_spec(const u32* __restrict__ planes,
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const long long t0 = slab_tick[s], T = slab_tick[s + 1] - t0;
     const rx_pv4* p = reinterpret_cast<const rx_pv4*>(planes) + t0 * (9 * 64) + lane;
-    volatile u32* flags = lds;       // copy c of the second wavefront is in place when flags[c] != 0
-    u32* accx = lds + 8;             // the second wavefront's accept bits, one word per lane
-    u32* ck = lds + 8 + 64;          // copy c, state word k, lane l at (c * NS + k) * 64 + l
-    constexpr int NS = PR::NS, NCP = PR::NCP;
-    const bool split = PR::SPEC && NCP > 0 && T >= 16;
-    if (threadIdx.x < 8) flags[threadIdx.x] = 0u;
+    constexpr int NS = PR::NS, NCP = PR::NCP, NW = RX_SPEC_WAVES;
+    volatile u32* flags = lds;          // flags[8 i + c]: wavefront i's copy c is in place
+    volatile u32* met = lds + 8 * NW;   // met[i]: wavefront i met wavefront i + 1
+    u32* accx = lds + 9 * NW;           // per wavefront and lane: accept bits,
+    u32* vnx = accx + 64 * NW;          // the strings with bytes at the meeting tick,
+    u32* surex = vnx + 64 * NW;         // the strings in the suffix loop there
+    u32* ck = surex + 64 * NW;          // wavefront i >= 1, copy c, word k, lane l at (((i-1) NCP + c) NS + k) 64 + l
+    int ws = PR::SPEC && NCP > 0 ? NW : 1;
+    while (ws > 1 && T < 64 * ws) ws >>= 1;
+    if (threadIdx.x < 9 * NW) lds[threadIdx.x] = 0u;
     __syncthreads();
-    // unsplit: the first wavefront runs the whole slab, the second nothing
-    const long long MT = split ? T / 2 : T;
-    const int ncp = split ? NCP : 0;
-    u32 st[NS];
-    u32 acc;
-    PR::init(st, acc);
-    u32 accf = wave == 0 ? acc : 0u;
-    long long t = wave == 0 ? 0 : MT;
-    bool same = false;
-    u32 vnext = 0u, sure = 0u;
-    // c: the copy due at the end of the next segment (-1: the first
-    // wavefront's first half, no copy)
-    int c = wave == 0 ? -1 : 0;
+    if (wave < ws) {
+        const long long seg = T / ws, start = wave * seg, next = wave + 1 < ws ? start + seg : T;
+        u32 st[NS];
+        u32 acc;
+        PR::init(st, acc);
+        u32 accf = wave == 0 ? acc : 0u;
+        u32 vnext = 0u, sure = 0u;
+        bool same = false;
+        long long t = start;
+        // phase 0: own copies (not the first wavefront); 1: to the segment's
+        // end; 2: the next wavefront's copies (not the last), then the end
+        int phase = wave == 0 ? 1 : 0, c = 0;
 #pragma clang loop unroll(disable)
-    for (;;) {
-        const long long tc = c < 0 ? MT : MT + (4ll << c);
-        const bool at_ck = c >= 0 && c < ncp && tc <= T;
-        const long long te = c < 0 ? MT : at_ck ? tc : T;
-        rx_ticks<PR>(p, t, te, st, acc, accf);
-        t = te;
-        if (c >= 0) {
-            if (!at_ck) break;
-            if (wave == 1) {
+        for (;;) {
+            long long te;
+            if (phase == 0) te = start + (4ll << c);
+            else if (phase == 1) te = next;
+            else te = c < NCP ? next + (4ll << c) : T;
+            if (te > T) te = T;
+            rx_ticks<PR>(p, t, te, st, acc, accf);
+            t = te;
+            if (phase == 0) {
 #pragma unroll
-                for (int k = 0; k < NS; ++k) ck[(c * NS + k) * 64 + lane] = st[k];
+                for (int k = 0; k < NS; ++k) ck[(((wave - 1) * NCP + c) * NS + k) * 64 + lane] = st[k];
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                if (lane == 0) flags[c] = 1u;
+                if (lane == 0) flags[8 * wave + c] = 1u;
+                if (++c == NCP) {
+                    phase = 1;
+                    c = 0;
+                }
+            } else if (phase == 1) {
+                if (wave + 1 == ws) break;
+                phase = 2;
             } else {
+                if (c == NCP || t >= T) break;
                 int spin = 0;
-                while (flags[c] == 0u && spin < (1 << 22)) {
+                while (flags[8 * (wave + 1) + c] == 0u && spin < (1 << 22)) {
                     __builtin_amdgcn_s_sleep(2);
                     ++spin;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                if (flags[c] != 0u) {
-                    // only strings with bytes left count, and of those not the
-                    // ones already in the search suffix's any-byte loop (they
-                    // accept whatever follows)
-                    vnext = t < T ? p[t * (9 * 64) + 8 * 64].x : 0u;
+                if (flags[8 * (wave + 1) + c] != 0u) {
+                    vnext = p[t * (9 * 64) + 8 * 64].x;
                     sure = PR::SUF >= 0 ? st[PR::SUF >= 0 ? PR::SUF : 0] : 0u;
                     u32 diff = 0u;
 #pragma unroll
-                    for (int k = 0; k < NS; ++k) diff |= st[k] ^ ck[(c * NS + k) * 64 + lane];
+                    for (int k = 0; k < NS; ++k) diff |= st[k] ^ ck[((wave * NCP + c) * NS + k) * 64 + lane];
                     same = __builtin_amdgcn_ballot_w64((diff & vnext & ~sure) != 0u) == 0ull;
                 }
                 if (same) break;
+                ++c;
             }
         }
-        ++c;
+        accx[wave * 64 + lane] = accf;
+        vnx[wave * 64 + lane] = vnext;
+        surex[wave * 64 + lane] = sure;
+        if (lane == 0) met[wave] = same ? 1u : 0u;
     }
-    if (wave == 1) accx[lane] = accf;
     __syncthreads();
     if (wave == 0) {
-        // strings that go on past the meeting point take the second
-        // wavefront's bit, or accept if they are in the suffix loop
-        const u32 go_on = same ? vnext : 0u;
-        res[lane * RX_NPROGS] = (accf & ~go_on) | ((accx[lane] | sure) & go_on);
+        // wavefront i holds the true state from where wavefront i - 1 met it
+        // to where it meets wavefront i + 1 (or the end)
+        u32 r = 0u, live = 0xffffffffu;
+        for (int i = 0; i < ws; ++i) {
+            const u32 a = accx[i * 64 + lane];
+            if (i + 1 == ws || met[i] == 0u) {
+                r |= a & live;
+                break;
+            }
+            const u32 vn = vnx[i * 64 + lane], su = surex[i * 64 + lane];
+            r |= (a & live & ~vn) | (su & vn & live);
+            live &= vn & ~su;
+        }
+        res[lane * RX_NPROGS] = r;
     }
 }
 
@@ -1177,11 +1202,11 @@ extern "C" __global__ __launch_bounds__(64) void rx_planes_multi(const u32* __re
     rx_dispatch(p, planes, slab_tick, S - 1 - r, res + (S - 1 - r) * 64 * RX_NPROGS + p);
 }
 
-// The same slabs with two wavefronts per (program, slab): a searched
-// program's slab of 16 ticks or more gets a second wavefront that starts in
-// the middle (rx_run_slab_spec); otherwise the first wavefront runs it whole.  Dynamic LDS: RX_SPEC_LDS
+// The same slabs with RX_SPEC_WAVES wavefronts per (program, slab): a
+// searched program's slab of 128 ticks or more is cut into segments run side
+// by side (rx_run_slab_spec); otherwise the first wavefront runs it whole.  Dynamic LDS: RX_SPEC_LDS
 // bytes (flags, B's accept bits, the checkpoints).
-extern "C" __global__ __launch_bounds__(128) void rx_planes_spec(const u32* __restrict__ planes,
+extern "C" __global__ __launch_bounds__(64 * RX_SPEC_WAVES) void rx_planes_spec(const u32* __restrict__ planes,
         const long long* __restrict__ slab_tick, const long long* __restrict__ info, u32* __restrict__ res,
         long long max_slabs, long long r_lo, long long r_hi) {
     extern __shared__ u32 rx_spec_lds[];
@@ -1202,7 +1227,7 @@ extern "C" __global__ __launch_bounds__(128) void rx_planes_spec(const u32* __re
 // template, a dispatch over the programs and the kernel.
 std::string jit_multi_planes_source(const Program* const* progs, int n, int* max_state, int* spec_lds) {
     std::ostringstream s;
-    s << "typedef unsigned int u32;\n#define RX_NPROGS " << n << "\n";
+    s << "typedef unsigned int u32;\n#define RX_NPROGS " << n << "\n#define RX_SPEC_WAVES " << kSpecWaves << "\n";
     int mx = 0;
     int64_t ck_words = 0;   // the largest checkpoint area of a split slab
     for (int k = 0; k < n; ++k) {
@@ -1213,8 +1238,10 @@ std::string jit_multi_planes_source(const Program* const* progs, int n, int* max
         // a searched program's long slabs may be split in two; as many
         // checkpoints (after 4, 8, 16, ... ticks) as the LDS budget holds
         const bool spec = search_prefix_leaf(*progs[k]) >= 0;
-        int ncp = spec ? (int)std::min<int64_t>(kSpecCheckpoints, kSpecLdsBudget / (4 * 64 * (int64_t)ns)) : 0;
-        ck_words = std::max<int64_t>(ck_words, (int64_t)ncp * ns * 64);
+        int ncp = spec ? (int)std::min<int64_t>(kSpecCheckpoints,
+                                                 kSpecLdsBudget / (4 * 64 * (int64_t)ns * (kSpecWaves - 1)))
+                       : 0;
+        ck_words = std::max<int64_t>(ck_words, (int64_t)ncp * ns * 64 * (kSpecWaves - 1));
         // the step source opens with its own #define of RX_NS
         const size_t eol = step.find('\n');
         s << "#define RX_NS " << ns << "\nnamespace rxq" << k << " {\n" << step.substr(eol + 1) << "}\n#undef RX_NS\n";
@@ -1247,7 +1274,8 @@ std::string jit_multi_planes_source(const Program* const* progs, int n, int* max
     (void)at;
     s << disp.str();
     if (max_state) *max_state = mx;
-    if (spec_lds) *spec_lds = (int)(4 * (8 + 64 + ck_words));
+    // flags and meeting marks (9 words per wavefront), three words per lane and wavefront, the copies
+    if (spec_lds) *spec_lds = (int)(4 * (9 * kSpecWaves + 3 * 64 * kSpecWaves + ck_words));
     return s.str();
 }
 
@@ -1452,7 +1480,8 @@ int launch_planes_circuits(const Program* const* progs, int n, const uint32_t* p
     long long a4 = max_slabs, a5 = r_lo, a6 = hi;
     void* args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6};
     if (split)
-        return (int)hipModuleLaunchKernel(K->fn_spec, grid, 1, 1, 128, 1, 1, (unsigned)K->spec_lds, (hipStream_t)stream,
+        return (int)hipModuleLaunchKernel(K->fn_spec, grid, 1, 1, 64 * kSpecWaves, 1, 1, (unsigned)K->spec_lds,
+                                          (hipStream_t)stream,
                                           args, nullptr);
     return (int)hipModuleLaunchKernel(K->fn, grid, 1, 1, 64, 1, 1, 0, (hipStream_t)stream, args, nullptr);
 }
