@@ -235,7 +235,7 @@ void jit_staging(const Program* P, int32_t staged[7]);
 // Plane-form circuits (rx_jit.cpp): one module per list of programs.
 // spec_lds (may be NULL): LDS bytes of the kernel that splits long slabs
 std::string jit_multi_planes_source(const Program* const* progs, int n, int* max_state, int* spec_lds);
-constexpr int kSpecWaves = 4;                    // wavefronts per long slab of a searched program
+constexpr int kSpecWaves = 8;                    // wavefronts per long slab of a searched program
 constexpr int64_t kSpecLdsBudget = 140 * 1024;   // the copies of a split slab's states
 constexpr int kSpecCheckpoints = 4;              // after 4, 8, 16, 32 ticks of a segment
 std::string jit_planes_source(const Program& P, int* n_state);   // the list of one program

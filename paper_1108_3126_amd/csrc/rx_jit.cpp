@@ -1067,8 +1067,10 @@ __device__ __forceinline__ void rx_run_slab(const u32* __restrict__ planes, cons
     res[lane * RX_NPROGS] = accf;
 }
 
-// A long slab of a searched program on up to RX_SPEC_WAVES wavefronts.  The
-// slab's T ticks are cut into ws segments of at least 64 ticks; wavefront i
+// A long slab of a searched program on up to PR::NW wavefronts (8, 4 or 2,
+// as many as leave room in LDS for the kept states; the launch has
+// RX_SPEC_WAVES).  The slab's T ticks are cut into ws segments of at least 64
+// ticks; wavefront i
 // starts at tick i * T / ws, the first from the start as usual, the others
 // from the start state, and each of those leaves copies of its state in LDS
 // after 4, 8, 16, 32 of its ticks.  Wavefront i runs on past its segment and,
@@ -1101,7 +1103,7 @@ __device__ __forceinline__ void rx_run_slab_spec(const u32* __restrict__ planes,
     u32* vnx = accx + 64 * NW;          // the strings with bytes at the meeting tick,
     u32* surex = vnx + 64 * NW;         // the strings in the suffix loop there
     u32* ck = surex + 64 * NW;          // wavefront i >= 1, copy c, word k, lane l at (((i-1) NCP + c) NS + k) 64 + l
-    int ws = PR::SPEC && NCP > 0 ? NW : 1;
+    int ws = PR::SPEC && NCP > 0 ? PR::NW : 1;
     while (ws > 1 && T < 64 * ws) ws >>= 1;
     if (threadIdx.x < 9 * NW) lds[threadIdx.x] = 0u;
     __syncthreads();
@@ -1238,16 +1240,21 @@ std::string jit_multi_planes_source(const Program* const* progs, int n, int* max
         // a searched program's long slabs may be split in two; as many
         // checkpoints (after 4, 8, 16, ... ticks) as the LDS budget holds
         const bool spec = search_prefix_leaf(*progs[k]) >= 0;
-        int ncp = spec ? (int)std::min<int64_t>(kSpecCheckpoints,
-                                                 kSpecLdsBudget / (4 * 64 * (int64_t)ns * (kSpecWaves - 1)))
-                       : 0;
-        ck_words = std::max<int64_t>(ck_words, (int64_t)ncp * ns * 64 * (kSpecWaves - 1));
+        // as many wavefronts per long slab (8, 4, 2) as leave room in LDS for
+        // two kept states of each but the first, and as many kept states
+        // (up to kSpecCheckpoints) as then fit
+        auto fits = [&](int w) { return kSpecLdsBudget / (4 * 64 * (int64_t)ns * (w - 1)); };
+        int nw = kSpecWaves;
+        while (nw > 2 && fits(nw) < 2) nw >>= 1;
+        const int ncp = spec ? (int)std::min<int64_t>(kSpecCheckpoints, fits(nw)) : 0;
+        ck_words = std::max<int64_t>(ck_words, (int64_t)ncp * ns * 64 * (nw - 1));
         // the step source opens with its own #define of RX_NS
         const size_t eol = step.find('\n');
         s << "#define RX_NS " << ns << "\nnamespace rxq" << k << " {\n" << step.substr(eol + 1) << "}\n#undef RX_NS\n";
         s << "struct RxProg" << k << " {\n    static constexpr int NS = " << ns << ";\n"
           << "    static constexpr bool SPEC = " << (spec ? "true" : "false") << ";\n"
           << "    static constexpr int NCP = " << ncp << ";\n"
+          << "    static constexpr int NW = " << nw << ";\n"
           << "    static constexpr int SUF = " << suf << ";\n"
           << "    __device__ static __forceinline__ void init(u32 (&s)[NS], u32& acc) { rxq" << k << "::rx_init(s, acc); }\n"
           << "    __device__ static __forceinline__ void step(u32 (&s)[NS], u32& acc, u32 b0, u32 b1, u32 b2, u32 b3, "

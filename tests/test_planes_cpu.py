@@ -247,7 +247,7 @@ SPEC_DRIVER = r"""
 // in the suffix loop.
 extern "C" int run_planes_spec(const uint8_t* bytes, const int64_t* lo, const int64_t* len, int64_t n,
                                unsigned char* out, int64_t* stopped) {
-    const int NS = RxProg0::NS, NCP = RxProg0::NCP, NW = RX_SPEC_WAVES;
+    const int NS = RxProg0::NS, NCP = RxProg0::NCP;
     *stopped = 0;
     for (int64_t s0 = 0; s0 < n; s0 += 2048) {
         const int64_t count = n - s0 < 2048 ? n - s0 : 2048;
@@ -273,7 +273,7 @@ extern "C" int run_planes_spec(const uint8_t* bytes, const int64_t* lo, const in
                 }
             }
         auto valid = [&](int lane, int64_t t) { return t < T ? W[((size_t)t * 64 + lane) * 36 + 32] : 0u; };
-        int ws = RxProg0::SPEC && NCP > 0 ? NW : 1;
+        int ws = RxProg0::SPEC && NCP > 0 ? RxProg0::NW : 1;
         while (ws > 1 && T < 64 * ws) ws >>= 1;
         const int64_t seg = T / ws;
         // one run: every lane's state, from tick `from`
