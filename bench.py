@@ -433,6 +433,32 @@ def run_pathological(args, torch, dev):
             nm["ratio_1e5_1e4"] = round(nm["100000"]["ms"] / nm["10000"]["ms"], 2)
         nm["ratio_1e4_1e3"] = round(nm["10000"]["ms"] / nm["1000"]["ms"], 2)
         fam["node_machine"] = nm
+        # the compiled circuit (here one or two state words: every 'a' leaf holds the same word) run
+        # chunk-parallel: one wavefront per string, 2,048 chunks, each a map of the circuit's states
+        pj = rx.compile(prog.ast, prog.root).upload(dev).jit()
+        ck = {"state_words": pj.jit_stats()["state_words"]}
+        for n_len in (1000, 10000, 100000):
+            s = W.pathological_strings(family, n_len, count=256)
+            d = torch.from_numpy(s.data).to(dev)
+            launch = (rx.VARIANT_CHUNKS, 0, 0, 0)
+            out = rx.match_fixed(pj, d, n_len, s.n, launch=launch)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                rx.match_fixed(pj, d, n_len, s.n, out=out, launch=launch)
+            e1.record()
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            entry = {"ms": round(e0.elapsed_time(e1) / 5, 4),
+                     "closed_form_ok": bool(got[:128].sum() == 0 and got[128:].all())}
+            if n_len == 1000:
+                idx = np.array([0, 1, 127, 128, 200, 255], np.int64)
+                want = oracle.match(prog.ast, prog.root, prog.classes, False, s.data, s.offsets, index=idx)
+                entry["oracle_ok"] = bool(np.array_equal(got[idx], want))
+            ck[str(n_len)] = entry
+        log(f"pathological {family} chunk-parallel circuit: {ck}")
+        fam["chunk_parallel_circuit"] = ck
         res["families"][family] = fam
     return res
 

@@ -214,8 +214,14 @@ enum {
     RX_VARIANT_AUTO = 0,
     RX_VARIANT_LANE = 1,   /* one lane owns one string and its set (sets of <= 16 words) */
     RX_VARIANT_WAVE = 2,   /* one wavefront owns one string; lane j owns word j of the set */
-    RX_VARIANT_SLICED = 3  /* bit-sliced node circuit: one lane runs 32 strings at once
+    RX_VARIANT_SLICED = 3, /* bit-sliced node circuit: one lane runs 32 strings at once
                               (needs rx_program_jit) */
+    RX_VARIANT_CHUNKS = 4  /* rx_match_fixed_ex only: the bit-sliced circuit run chunk-parallel, for
+                              circuits of at most two state words (rx_program_jit_stats): one
+                              wavefront per string, the string cut into 2,048 chunks, each chunk run
+                              from every one of the 2^words states (the step of Def. 5.1 depends on
+                              the state and the byte alone, so a chunk is a map of states) and the
+                              maps composed in order; any alignment and length */
 };
 
 /* Launch parameters; zero fields mean "default". */
@@ -355,7 +361,10 @@ int rx_match_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t lengt
                    void* stream);
 
 /* rx_match_fixed with an explicit variant and launch shape (RX_VARIANT_SLICED
- * requires rx_program_jit, 16-byte alignment and length % 16 == 0). */
+ * requires rx_program_jit, 16-byte alignment and length % 16 == 0;
+ * RX_VARIANT_CHUNKS requires rx_program_jit and a circuit of at most two state
+ * words, else RX_EINVAL).  With RX_VARIANT_AUTO such a circuit runs
+ * chunk-parallel when length >= 32768 or n <= 4096. */
 int rx_match_fixed_ex(const rx_program* prog, const uint8_t* d_bytes, int64_t length, int64_t n, uint8_t* d_out,
                       const rx_launch* launch, void* stream);
 

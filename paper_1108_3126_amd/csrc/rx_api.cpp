@@ -516,10 +516,22 @@ int rx_match_fixed_ex(const rx_program* prog, const uint8_t* d_bytes, int64_t le
     }
     const bool sliced_ok = jit_ready(P, nullptr, nullptr) && length > 0 && (length % 16) == 0 &&
                            (reinterpret_cast<uintptr_t>(d_bytes) & 15) == 0;
+    // A circuit of at most two words runs few or long strings chunk-parallel;
+    // many short ones fill the chip better 32 strings to a lane.
+    const bool chunks_ok = jit_chunks_ready(P) && length > 0;
     if (variant == RX_VARIANT_AUTO)
-        variant = sliced_ok ? RX_VARIANT_SLICED : auto_table_variant(P, n);
+        variant = chunks_ok && (length >= 32768 || n <= 4096) ? RX_VARIANT_CHUNKS
+                  : sliced_ok                                 ? RX_VARIANT_SLICED
+                                                              : auto_table_variant(P, n);
     int e;
     switch (variant) {
+    case RX_VARIANT_CHUNKS:
+        if (!chunks_ok) return fail(RX_EINVAL, "the chunk-parallel kernel needs rx_program_jit and a circuit of at "
+                                               "most two state words");
+        if (n > 0x7fffffffll) return fail(RX_EINVAL, "the chunk-parallel kernel runs at most 2^31 - 1 strings");
+        if (length > (int64_t(1) << 40)) return fail(RX_EINVAL, "the chunk-parallel kernel runs strings of at most 2^40 bytes");
+        e = launch_sliced_chunks(P, d_bytes, length, n, d_out, stream);
+        break;
     case RX_VARIANT_SLICED:
         if (!jit_ready(P, nullptr, nullptr)) return fail(RX_EINVAL, "sliced kernel needs rx_program_jit first");
         if (!sliced_ok) return fail(RX_EINVAL, "sliced kernel needs 16-byte aligned bytes and length % 16 == 0");

@@ -219,6 +219,12 @@ int layout_slot(int64_t id, int64_t** slot);
 int launch_layout_check(const int64_t* offsets, int64_t n, const uint8_t* bytes, int64_t* slot, int64_t id,
                         void* stream);
 // bit-sliced node circuit (rx_jit.cpp)
+// The chunk-parallel kernel of a compiled circuit of at most two state words
+// (one wavefront per string, 2,048 chunks, each run from every state; the
+// chunks' maps compose in order).
+bool jit_chunks_ready(const Program* P);
+int launch_sliced_chunks(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,
+                         void* stream);
 // (suffix_slot: the state word of a searched program's suffix leaf, or -1)
 std::string jit_step_source(const Program& P, int* n_state, int* n_ops, int* suffix_slot = nullptr);
 std::string jit_full_source(const Program& P, int* n_state, int* n_ops);

@@ -436,6 +436,164 @@ __device__ __forceinline__ void rx_transpose32(u32 (&a)[32]) {
 }
 )RX";
 
+// Chunk-parallel form of a circuit of at most two state words.  The step of
+// Def. 5.1 maps (state, byte) to a state and an accept bit, so a chunk of a
+// string is a map from the R = 2^NS states to states, with the accept bit
+// after its last byte; running the chunk once from each of the R states (all
+// 32 chunks of a lane from the same state, word k all-ones where bit k of
+// the state index is set) gives it, and the maps of consecutive chunks
+// compose.  A map is one word: bits 2r, 2r+1 the state after the chunk from
+// state r, bit 8 + r the accept bit after its last byte, bit 12 set when the
+// chunk has bytes (clear: the identity).
+const char* kChunkSource = R"RX(
+#if RX_NS <= 2
+#define RX_R (1 << RX_NS)
+__device__ __forceinline__ u32 rx_fn_compose(u32 f, u32 g) {   // f, then g
+    if (!(g & 0x1000u)) return f;
+    if (!(f & 0x1000u)) return g;
+    u32 h = 0x1000u;
+#pragma unroll
+    for (int r = 0; r < RX_R; ++r) {
+        const u32 m = (f >> (2 * r)) & 3u;
+        h |= ((g >> (2 * m)) & 3u) << (2 * r);
+        h |= ((g >> (8 + m)) & 1u) << (8 + r);
+    }
+    return h;
+}
+
+// Bytes [off, off + 16) of a chunk of len bytes at c, little-endian in four
+// words (bytes at or past len unspecified); only the 16-byte aligned blocks
+// that hold a byte of the chunk are read.
+__device__ __forceinline__ void rx_chunk_window16(const unsigned char* c, long long len, long long off,
+                                                  u32 (&w)[4]) {
+    w[0] = w[1] = w[2] = w[3] = 0u;
+    if (off >= len) return;
+    const unsigned long long addr = (unsigned long long)(c + off), end = (unsigned long long)(c + len);
+    const unsigned long long a = addr & ~15ull;
+    const u32 sh = (u32)(addr & 15ull);
+    u32 b[8];
+    const u32* p0 = (const u32*)a;
+    b[0] = p0[0]; b[1] = p0[1]; b[2] = p0[2]; b[3] = p0[3];
+    if (a + 16 < end) {
+        const u32* p1 = (const u32*)(a + 16);
+        b[4] = p1[0]; b[5] = p1[1]; b[6] = p1[2]; b[7] = p1[3];
+    } else {
+        b[4] = b[5] = b[6] = b[7] = 0u;
+    }
+    if (sh & 8) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) b[k] = b[k + 2];
+    }
+    if (sh & 4) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) b[k] = b[k + 1];
+    }
+    const u32 r = (sh & 3) * 8;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = r ? (b[k] >> r) | (b[k + 1] << (32 - r)) : b[k];
+}
+
+// The composed map of chunks 32 lane .. 32 lane + 31 (Lc bytes each) of the
+// string at s of `length` bytes.
+__device__ __forceinline__ u32 rx_chunk_lane(const unsigned char* s, long long length, long long Lc, int lane) {
+    int len[32];   // Lc < 2^31 (the host allows strings of up to 2^40 bytes)
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        const long long start = (32ll * lane + j) * Lc;
+        len[j] = start < length ? (int)(length - start < Lc ? length - start : Lc) : 0;
+    }
+    u32 st[RX_R][RX_NS], acc[RX_R];
+#pragma unroll
+    for (int r = 0; r < RX_R; ++r) {
+#pragma unroll
+        for (int k = 0; k < RX_NS; ++k) st[r][k] = ((r >> k) & 1) ? 0xffffffffu : 0u;
+        acc[r] = 0u;
+    }
+    for (long long p = 0; p < Lc && p < len[0]; p += 16) {
+        u32 win[32][4];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) rx_chunk_window16(s + (32ll * lane + j) * Lc, len[j], p, win[j]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            u32 x[32];
+#pragma unroll
+            for (int j = 0; j < 32; ++j) x[j] = win[j][q];
+            rx_transpose32(x);   // x[8 i + b]: bit b of byte i of the four, bit j = chunk j
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long long pos = p + 4 * q + i;
+                u32 v = 0u;
+#pragma unroll
+                for (int j = 0; j < 32; ++j) v |= (len[j] > pos ? 1u : 0u) << j;
+#pragma unroll
+                for (int r = 0; r < RX_R; ++r) {
+                    u32 ns[RX_NS];
+#pragma unroll
+                    for (int k = 0; k < RX_NS; ++k) ns[k] = st[r][k];
+                    u32 a = acc[r];
+                    rx_step(ns, a, x[8 * i], x[8 * i + 1], x[8 * i + 2], x[8 * i + 3], x[8 * i + 4], x[8 * i + 5],
+                            x[8 * i + 6], x[8 * i + 7]);
+#pragma unroll
+                    for (int k = 0; k < RX_NS; ++k) st[r][k] = (ns[k] & v) | (st[r][k] & ~v);
+                    acc[r] = (a & v) | (acc[r] & ~v);
+                }
+            }
+        }
+    }
+    u32 f = 0u;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        if (len[j] == 0) continue;
+        u32 g = 0x1000u;
+#pragma unroll
+        for (int r = 0; r < RX_R; ++r) {
+            u32 m = 0u;
+#pragma unroll
+            for (int k = 0; k < RX_NS; ++k) m |= ((st[r][k] >> j) & 1u) << k;
+            g |= m << (2 * r);
+            g |= ((acc[r] >> j) & 1u) << (8 + r);
+        }
+        f = rx_fn_compose(f, g);
+    }
+    return f;
+}
+
+// The result of a string from the composed map of all its chunks.
+__device__ __forceinline__ unsigned char rx_chunk_result(u32 f) {
+    u32 s0[RX_NS], a0;
+    rx_init(s0, a0);
+    u32 r0 = 0u;
+#pragma unroll
+    for (int k = 0; k < RX_NS; ++k) r0 |= (s0[k] & 1u) << k;
+    return (unsigned char)((f & 0x1000u) ? (f >> (8 + r0)) & 1u : a0 & 1u);
+}
+#endif
+)RX";
+
+// One wavefront per string; lane l runs chunks 32 l .. 32 l + 31 of 2,048
+// chunks of Lc bytes (a multiple of 16), and the lanes' maps compose in lane
+// order in six shuffle steps (after step d, lane l with l % 2d == 0 holds the
+// map of lanes l .. l + 2d - 1).
+const char* kChunkKernelSource = R"RX(
+#if RX_NS <= 2
+extern "C" __global__ __launch_bounds__(64) void rx_sliced_chunks(const unsigned char* __restrict__ bytes,
+                                                                  long long length, long long n,
+                                                                  unsigned char* __restrict__ out) {
+    const long long i = blockIdx.x;
+    if (i >= n) return;
+    const int lane = threadIdx.x;
+    const long long Lc = ((length + 2047) / 2048 + 15) / 16 * 16;
+    u32 f = rx_chunk_lane(bytes + i * length, length, Lc, lane);
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const u32 g = __shfl_down(f, d, 64);
+        if ((lane & (2 * d - 1)) == 0) f = rx_fn_compose(f, g);
+    }
+    if (lane == 0) out[i] = rx_chunk_result(f);
+}
+#endif
+)RX";
+
 // Fixed-length strings: string i is bytes[i*length, (i+1)*length).  One
 // wavefront runs 2048 strings: lane l owns bit j of every word for string
 // base + 64 j + l.  32-byte tiles of every string are staged in LDS by
@@ -1311,6 +1469,7 @@ struct JitKernel {
     hipFunction_t skew_offsets = nullptr;   // the same form for rx_match's equal-length strings
     hipFunction_t first = nullptr;   // the skewed kernel's earliest-accept form
     bool first_words = false;
+    hipFunction_t chunks = nullptr;   // chunk-parallel form (circuits of at most two words)
     int dev = -1;
     int n_state = 0, n_ops = 0;
     std::string arch;
@@ -1337,7 +1496,9 @@ std::string jit_full_source(const Program& P, int* n_state, int* n_ops) {
     s << "typedef unsigned int u32;\n";
     s << jit_step_source(P, n_state, n_ops);
     s << kTransposeSource;
+    s << kChunkSource;
     s << kFixedKernelSource;
+    s << kChunkKernelSource;
     return s.str();
 }
 
@@ -1704,6 +1865,10 @@ int jit_compile(Program* P, const char* arch_in) {
         if (e == hipSuccess) e = hipModuleGetFunction(&off_w, K->mod, "rx_sliced_offsets_skew_w");
         if (e == hipSuccess) e = hipModuleGetFunction(&K->first, K->mod, "rx_sliced_first_skew");
         if (e == hipSuccess) e = hipModuleGetFunction(&first_w, K->mod, "rx_sliced_first_skew_w");
+        if (e == hipSuccess && K->n_state <= 2 && hipModuleGetFunction(&K->chunks, K->mod, "rx_sliced_chunks") != hipSuccess) {
+            K->chunks = nullptr;
+            (void)hipGetLastError();
+        }
         if (e != hipSuccess) {
             hipModuleUnload(K->mod);
             delete K;
@@ -1866,6 +2031,23 @@ int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, 
     void* o = out;
     void* args[] = {&b, &len, &nn, &o};
     return (int)hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, threads, 1, 1, lds, (hipStream_t)stream, args, nullptr);
+}
+
+bool jit_chunks_ready(const Program* P) {
+    const JitKernel* K = static_cast<const JitKernel*>(P->jit);
+    return K && K->chunks;
+}
+
+int launch_sliced_chunks(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,
+                         void* stream) {
+    const JitKernel* K = static_cast<const JitKernel*>(P->jit);
+    if (!K || !K->chunks) return (int)hipErrorInvalidValue;
+    if (n > 0x7fffffffll) return (int)hipErrorInvalidValue;
+    long long len = length, nn = n;
+    const void* b = bytes;
+    void* o = out;
+    void* args[] = {&b, &len, &nn, &o};
+    return (int)hipModuleLaunchKernel(K->chunks, (unsigned)n, 1, 1, 64, 1, 1, 0, (hipStream_t)stream, args, nullptr);
 }
 
 }  // namespace rx

@@ -20,7 +20,7 @@ RX_OK, RX_EINVAL, RX_ETOOBIG, RX_ENOTUPLOADED, RX_EHIP, RX_EBUSY, RX_ENOMEM, RX_
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 EPS, BYTE, CLASS, CAT, ALT, STAR, PLUS, OPT, PLUSLOOP = range(9)
 RX_SEARCH = 1
-VARIANT_AUTO, VARIANT_LANE, VARIANT_WAVE, VARIANT_SLICED = range(4)
+VARIANT_AUTO, VARIANT_LANE, VARIANT_WAVE, VARIANT_SLICED, VARIANT_CHUNKS = range(5)
 
 AST_DTYPE = np.dtype(
     [("kind", np.uint8), ("byte", np.uint8), ("cls", np.uint16), ("c0", np.int32), ("c1", np.int32)]

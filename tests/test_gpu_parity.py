@@ -306,6 +306,35 @@ def test_sliced_pathological(dev):
     assert ei.value.code == rx.RX_ETOOBIG
 
 
+def test_chunk_parallel_pathological(dev):
+    """Circuits of at most two words run chunk-parallel (one wavefront per string, 2,048 chunks, each a
+    map of the circuit's states): the 4,096-node programs at lengths 1 .. 10^5 against the closed form
+    and the oracle, unaligned bytes, and the automatic choice; a circuit of more words is refused."""
+    from paper_1108_3126_amd import rx
+
+    for family, k in (("nested", 819), ("altstar", 585)):
+        prog = W.pathological_program(family, k)
+        p = rx.compile(prog.ast, prog.root).upload(dev).jit()
+        assert p.jit_stats()["state_words"] <= 2
+        for length in (1, 33, 1008, 4097, 100_000):
+            s = W.pathological_strings(family, length, count=64)
+            want = oracle_match(prog, s)
+            assert want[:32].sum() == 0 and want[32:].all()
+            got = fixed_match(p, s, length, dev, rx.VARIANT_CHUNKS)
+            assert np.array_equal(got, want), (family, length)
+            # one byte into the buffer: every string unaligned
+            buf = torch.from_numpy(np.concatenate([np.zeros(1, np.uint8), s.data])).to(dev)
+            out = rx.match_fixed(p, buf[1:], length, s.n, launch=(rx.VARIANT_CHUNKS, 0, 0, 0)).cpu().numpy()
+            assert np.array_equal(out, want), (family, length, "unaligned")
+            d = torch.from_numpy(s.data).to(dev)
+            assert np.array_equal(rx.match_fixed(p, d, length, s.n).cpu().numpy(), want)
+    big = W.single_program(1)
+    q = rx.compile(big.ast, big.root, big.classes, True).upload(dev).jit()
+    with pytest.raises(rx.RxError) as ei:
+        fixed_match(q, W.pathological_strings("nested", 64, count=4), 64, dev, rx.VARIANT_CHUNKS)
+    assert ei.value.code == rx.RX_EINVAL
+
+
 def test_fixed_layout_fallbacks(dev):
     """rx_match_fixed where the sliced kernel does not apply (length not a multiple of 16, a byte
     buffer not 16-byte aligned, length 0) runs the table-form kernel; explicit sliced requests there

@@ -194,3 +194,72 @@ def test_state_words_pathological_and_limit():
     with pytest.raises(rx.RxError) as ei:
         p.jit("gfx950")
     assert ei.value.code == rx.RX_ETOOBIG
+
+
+CHUNK_DRIVER = r"""
+// The chunk-parallel kernel on the host: per string, the 64 lanes' maps (the
+// same rx_chunk_lane as on the device), composed in lane order.
+extern "C" int rx_cpu_chunks(const unsigned char* bytes, long long length, long long n, unsigned char* out) {
+    const long long Lc = ((length + 2047) / 2048 + 15) / 16 * 16;
+    for (long long i = 0; i < n; ++i) {
+        u32 f = 0u;
+        for (int lane = 0; lane < 64; ++lane) f = rx_fn_compose(f, rx_chunk_lane(bytes + i * length, length, Lc, lane));
+        out[i] = rx_chunk_result(f);
+    }
+    return 0;
+}
+"""
+
+
+def cpu_chunks(p: rx.Program):
+    src = p.jit_source()
+    host_part = src.split("// ---- device kernel ----")[0]
+    code = "#define __device__\n#define __forceinline__ inline\n" + PERM_CPU + host_part + CHUNK_DRIVER
+    d = tempfile.mkdtemp(prefix="rxchunk")
+    cpp, so = os.path.join(d, "c.cpp"), os.path.join(d, "c.so")
+    open(cpp, "w").write(code)
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-w", "-o", so, cpp])
+    lib = ctypes.CDLL(so)
+    lib.rx_cpu_chunks.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_longlong, ctypes.c_void_p]
+
+    def run(data, length, n):
+        data = np.ascontiguousarray(data, dtype=np.uint8)
+        out = np.zeros(max(n, 1), np.uint8)
+        lib.rx_cpu_chunks(data.ctypes.data, length, n, out.ctypes.data)
+        return out[:n]
+
+    return run
+
+
+@pytest.mark.parametrize("family,k,length", [("nested", 819, 100_000), ("altstar", 585, 40_000), ("nested", 3, 1),
+                                             ("altstar", 7, 33), ("nested", 40, 4097)])
+def test_chunk_parallel_pathological(family, k, length):
+    """The chunk-parallel form (a chunk is a map of the circuit's 2^words states, Def. 5.1; maps compose in
+    order) on the 4,096-node programs and small ones, lengths from one byte (one chunk) to 10^5 (2,048
+    chunks of 49 -> 64 bytes): the closed form a^(n-1) t accepted, a^n not, and the oracle's bits."""
+    prog = W.pathological_program(family, k)
+    p = rx.compile(prog.ast, prog.root)
+    s = W.pathological_strings(family, length, count=8)
+    got = cpu_chunks(p)(s.data, length, s.n)
+    assert got[:4].sum() == 0 and got[4:].all()
+    want = oracle.match(prog.ast, prog.root, prog.classes, False, s.data, s.offsets)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("pattern,search", [(b"(x|y|z)*w", False), (b"a*b", True), (b"(ab)*c", True), (b"a(b|c)", False),
+                                            (b"(a|b)*abb", False), (b"x*", False)])
+def test_chunk_parallel_small_patterns(pattern, search):
+    """Circuits of one or two words (counted by the generator), random strings over the pattern's letters
+    with members planted, lengths that leave the last chunks empty or short: the oracle's bits."""
+    p = rx.compile_regex(pattern, search=search)
+    words = int(p.jit_source().split("#define RX_NS ", 1)[1].split()[0])
+    if words > 2:
+        pytest.skip(f"{words} state words")
+    ast, root, classes = rx.parse(pattern)
+    run = cpu_chunks(p)
+    rng = np.random.default_rng(len(pattern))
+    for length in (5, 47, 1000, 70_001):
+        n = 24 if length > 10_000 else 200
+        s = fixed_strings(rng, n, length, b"abcxyzw")
+        want = oracle.match(ast, root, classes, search, s.data, s.offsets)
+        assert np.array_equal(run(s.data, length, n), want), length
