@@ -495,6 +495,7 @@ def run_long(args, torch, dev):
             piece = w
             break
     member, _ = W.single_strings(prog, seed=31, n=1, length=256, plant_frac=1.0)
+    pj = rx.compile(prog.ast, prog.root, prog.classes, True).upload(dev).jit()
     for mb in (4, 64):
         n_bytes = mb << 20
         data = np.tile(piece, n_bytes // 256)
@@ -511,6 +512,9 @@ def run_long(args, torch, dev):
         entry["first_chunked_ms"], entry["first_chunked"] = timed(lambda: rx.match_first_long(p, d, data.size))
         entry["chunks"] = min(int(round((data.size / 2) ** 0.5)), 4096)
         entry["GBs_chunked"] = round(data.size / (entry["chunked_ms"] * 1e-3) / 1e9, 2)
+        # the compiled circuit (17 words) as chunks: each chunk an affine map of the state words
+        entry["circuit_chunks_ms"], entry["circuit_chunks_bit"] = timed(lambda: rx.match_long(pj, d, data.size))
+        entry["GBs_circuit_chunks"] = round(data.size / (entry["circuit_chunks_ms"] * 1e-3) / 1e9, 2)
         log(f"long: {entry}")
         res["cases"].append(entry)
     for family, k in (("nested", 819), ("altstar", 585)):
@@ -524,6 +528,8 @@ def run_long(args, torch, dev):
         for ch in (16, 64):
             entry[f"chunked_{ch}_ms"], entry[f"chunked_{ch}_bit"] = timed(lambda: rx.match_long(pp, acc, n_len, ch),
                                                                        reps=1)
+        pc = rx.compile(pk.ast, pk.root).upload(dev).jit()
+        entry["circuit_chunks_ms"], entry["circuit_chunks_bit"] = timed(lambda: rx.match_long(pc, acc, n_len))
         log(f"long: {entry}")
         res["cases"].append(entry)
     return res

@@ -271,6 +271,9 @@ int rx_match_long_workspace(const rx_program* prog, int64_t length, int32_t chun
     int64_t C, cl;
     long_chunks(P, length, chunks, &C, &cl);
     *bytes = long_rows_bytes(P, C);
+    // rx_match_long's circuit form (chunks = 0 with a compiled circuit) needs its segment maps
+    const int64_t circuit = chunks == 0 ? long_chunk_work_bytes(P, length) : -1;
+    if (circuit > 0 && (size_t)circuit > *bytes) *bytes = (size_t)circuit;
     return RX_OK;
     RX_GUARD_END
 }
@@ -316,6 +319,13 @@ int rx_match_long(const rx_program* prog, const uint8_t* d_bytes, int64_t length
     const Program* P = reinterpret_cast<const Program*>(prog);
     if (int rc = check_long_args(P, d_bytes, length, chunks, d_out)) return rc;
     if (!d_work) return fail(RX_EINVAL, "NULL device buffer");
+    // a compiled circuit of at most kLongChunkMaxState words, default chunking:
+    // the string as circuit chunks (each an affine map of the state words)
+    const int64_t circuit_need = chunks == 0 && length <= (int64_t(1) << 40) ? long_chunk_work_bytes(P, length) : -1;
+    if (circuit_need >= 0 && (size_t)circuit_need <= work_bytes) {
+        if (int e = launch_long_chunks(P, d_bytes, length, d_work, d_out, stream)) return hip_fail(e, "kernel launch");
+        return RX_OK;
+    }
     int64_t C, cl;
     long_chunks(P, length, chunks, &C, &cl);
     const size_t need = long_rows_bytes(P, C);

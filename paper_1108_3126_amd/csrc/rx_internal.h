@@ -223,6 +223,14 @@ int launch_layout_check(const int64_t* offsets, int64_t n, const uint8_t* bytes,
 // (one wavefront per string, 2,048 chunks, each run from every state; the
 // chunks' maps compose in order).
 bool jit_chunks_ready(const Program* P);
+// One long string as circuit chunks (circuits of at most kLongChunkMaxState
+// words: the chunk maps are affine, NS + 1 runs each): the workspace it needs
+// (-1: no such kernel for this program) and the launch (segments, then their
+// composition, on `stream`).
+constexpr int kLongChunkMaxState = 18;   // 2,048 chunk maps of NS + 1 words in LDS
+int64_t long_chunk_work_bytes(const Program* P, int64_t length);
+int launch_long_chunks(const Program* P, const uint8_t* bytes, int64_t length, void* work, uint8_t* out,
+                       void* stream);
 int launch_sliced_chunks(const Program* P, const uint8_t* bytes, int64_t length, int64_t n, uint8_t* out,
                          void* stream);
 // (suffix_slot: the state word of a searched program's suffix leaf, or -1)

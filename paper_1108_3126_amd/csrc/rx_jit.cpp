@@ -446,21 +446,6 @@ __device__ __forceinline__ void rx_transpose32(u32 (&a)[32]) {
 // state r, bit 8 + r the accept bit after its last byte, bit 12 set when the
 // chunk has bytes (clear: the identity).
 const char* kChunkSource = R"RX(
-#if RX_NS <= 2
-#define RX_R (1 << RX_NS)
-__device__ __forceinline__ u32 rx_fn_compose(u32 f, u32 g) {   // f, then g
-    if (!(g & 0x1000u)) return f;
-    if (!(f & 0x1000u)) return g;
-    u32 h = 0x1000u;
-#pragma unroll
-    for (int r = 0; r < RX_R; ++r) {
-        const u32 m = (f >> (2 * r)) & 3u;
-        h |= ((g >> (2 * m)) & 3u) << (2 * r);
-        h |= ((g >> (8 + m)) & 1u) << (8 + r);
-    }
-    return h;
-}
-
 // Bytes [off, off + 16) of a chunk of len bytes at c, little-endian in four
 // words (bytes at or past len unspecified); only the 16-byte aligned blocks
 // that hold a byte of the chunk are read.
@@ -491,6 +476,21 @@ __device__ __forceinline__ void rx_chunk_window16(const unsigned char* c, long l
     const u32 r = (sh & 3) * 8;
 #pragma unroll
     for (int k = 0; k < 4; ++k) w[k] = r ? (b[k] >> r) | (b[k + 1] << (32 - r)) : b[k];
+}
+
+#if RX_NS <= 2
+#define RX_R (1 << RX_NS)
+__device__ __forceinline__ u32 rx_fn_compose(u32 f, u32 g) {   // f, then g
+    if (!(g & 0x1000u)) return f;
+    if (!(f & 0x1000u)) return g;
+    u32 h = 0x1000u;
+#pragma unroll
+    for (int r = 0; r < RX_R; ++r) {
+        const u32 m = (f >> (2 * r)) & 3u;
+        h |= ((g >> (2 * m)) & 3u) << (2 * r);
+        h |= ((g >> (8 + m)) & 1u) << (8 + r);
+    }
+    return h;
 }
 
 // The composed map of chunks 32 lane .. 32 lane + 31 (Lc bytes each) of the
@@ -568,6 +568,85 @@ __device__ __forceinline__ unsigned char rx_chunk_result(u32 f) {
     return (unsigned char)((f & 0x1000u) ? (f >> (8 + r0)) & 1u : a0 & 1u);
 }
 #endif
+
+#if RX_NS <= 18
+#define RX_M (RX_NS + 1)
+// Affine maps of the state words.  Every update of the step is an OR of
+// terms that read at most one word (a leaf's word AND its label, or a label
+// alone), and so is the accept bit, so a chunk maps a state T (bit k: word
+// k) to m[0] | the m[k + 1] of T's words: m[0] the image of the empty state,
+// m[k + 1] of word k alone, bit 31 of each the accept bit after the chunk's
+// last byte.  NS + 1 runs of a chunk give its map, and maps compose.
+__device__ __forceinline__ u32 rx_aff_apply(const u32 (&m)[RX_M], u32 t) {
+    u32 r = m[0];
+#pragma unroll
+    for (int k = 0; k < RX_NS; ++k) r |= (0u - ((t >> k) & 1u)) & m[k + 1];
+    return r;
+}
+__device__ __forceinline__ void rx_aff_compose(u32 (&f)[RX_M], const u32 (&g)[RX_M]) {   // f := f, then g
+#pragma unroll
+    for (int i = 0; i < RX_M; ++i) f[i] = rx_aff_apply(g, f[i] & 0x7fffffffu);
+}
+
+// Run r (0: from the empty state, k + 1: from word k alone) of chunks
+// 32 lane .. 32 lane + 31 (Lc bytes each, bit j = chunk 32 lane + j) of the
+// seglen bytes at s; x[j] gets chunk j's image under the run (bit k: word k,
+// bit 31: the accept bit after its last byte).
+__device__ __forceinline__ void rx_aff_run(const unsigned char* s, long long seglen, long long Lc, int lane, int r,
+                                           u32 (&x)[32]) {
+    int len[32];   // Lc < 2^31 (the host allows strings of up to 2^40 bytes)
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        const long long start = (32ll * lane + j) * Lc;
+        len[j] = start < seglen ? (int)(seglen - start < Lc ? seglen - start : Lc) : 0;
+    }
+    u32 st[RX_NS], acc = 0u;
+#pragma unroll
+    for (int k = 0; k < RX_NS; ++k) st[k] = r == k + 1 ? 0xffffffffu : 0u;
+    for (long long p = 0; p < Lc && p < len[0]; p += 16) {
+        u32 win[32][4];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) rx_chunk_window16(s + (32ll * lane + j) * Lc, len[j], p, win[j]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            u32 y[32];
+#pragma unroll
+            for (int j = 0; j < 32; ++j) y[j] = win[j][q];
+            rx_transpose32(y);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long long pos = p + 4 * q + i;
+                u32 v = 0u;
+#pragma unroll
+                for (int j = 0; j < 32; ++j) v |= (len[j] > pos ? 1u : 0u) << j;
+                u32 ns[RX_NS];
+#pragma unroll
+                for (int k = 0; k < RX_NS; ++k) ns[k] = st[k];
+                u32 a = acc;
+                rx_step(ns, a, y[8 * i], y[8 * i + 1], y[8 * i + 2], y[8 * i + 3], y[8 * i + 4], y[8 * i + 5],
+                        y[8 * i + 6], y[8 * i + 7]);
+#pragma unroll
+                for (int k = 0; k < RX_NS; ++k) st[k] = (ns[k] & v) | (st[k] & ~v);
+                acc = (a & v) | (acc & ~v);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 32; ++k) x[k] = k < RX_NS ? st[k] : k == 31 ? acc : 0u;
+    rx_transpose32(x);
+}
+
+// The start state as a word set, and the result of a string from the
+// composed map of its chunks (any: the string has bytes).
+__device__ __forceinline__ unsigned char rx_aff_result(const u32 (&f)[RX_M], bool any) {
+    u32 s0[RX_NS], a0;
+    rx_init(s0, a0);
+    u32 t0 = 0u;
+#pragma unroll
+    for (int k = 0; k < RX_NS; ++k) t0 |= (s0[k] & 1u) << k;
+    return (unsigned char)(any ? rx_aff_apply(f, t0) >> 31 : a0 & 1u);
+}
+#endif
 )RX";
 
 // One wavefront per string; lane l runs chunks 32 l .. 32 l + 31 of 2,048
@@ -590,6 +669,99 @@ extern "C" __global__ __launch_bounds__(64) void rx_sliced_chunks(const unsigned
         if ((lane & (2 * d - 1)) == 0) f = rx_fn_compose(f, g);
     }
     if (lane == 0) out[i] = rx_chunk_result(f);
+}
+#endif
+
+#if RX_NS <= 18
+// One long string: one wavefront per segment of 2,048 chunks of Lc bytes.
+// Lane l runs the NS + 1 runs of its 32 chunks, keeping every chunk's map in
+// LDS (2,048 x (NS + 1) words), composes its chunks in order, and the lanes'
+// maps compose in lane order in six shuffle steps; the segment's map goes to
+// seg_maps[g * (NS + 1) ..].
+extern "C" __global__ __launch_bounds__(64) void rx_long_chunks(const unsigned char* __restrict__ bytes,
+                                                                long long length, long long Lc,
+                                                                u32* __restrict__ seg_maps) {
+    extern __shared__ u32 rx_maps[];
+    const long long g = blockIdx.x;
+    const int lane = threadIdx.x;
+    const long long base = g * 2048 * Lc;
+    const long long seglen = length - base < 2048 * Lc ? length - base : 2048 * Lc;
+    for (int r = 0; r < RX_M; ++r) {
+        u32 x[32];
+        rx_aff_run(bytes + base, seglen, Lc, lane, r, x);
+#pragma unroll
+        for (int j = 0; j < 32; ++j) rx_maps[(32 * lane + j) * RX_M + r] = x[j];
+    }
+    u32 f[RX_M];
+    bool any = false;
+    for (int j = 0; j < 32; ++j) {
+        if ((32ll * lane + j) * Lc >= seglen) break;
+        u32 h[RX_M];
+#pragma unroll
+        for (int i = 0; i < RX_M; ++i) h[i] = rx_maps[(32 * lane + j) * RX_M + i];
+        if (any) rx_aff_compose(f, h);
+        else {
+#pragma unroll
+            for (int i = 0; i < RX_M; ++i) f[i] = h[i];
+            any = true;
+        }
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        u32 h[RX_M];
+#pragma unroll
+        for (int i = 0; i < RX_M; ++i) h[i] = __shfl_down(any ? f[i] : 0u, d, 64);
+        const int ha = __shfl_down(any ? 1 : 0, d, 64);
+        if ((lane & (2 * d - 1)) == 0 && lane + d < 64 && ha) {
+            if (any) rx_aff_compose(f, h);
+            else {
+#pragma unroll
+                for (int i = 0; i < RX_M; ++i) f[i] = h[i];
+                any = true;
+            }
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < RX_M; ++i) seg_maps[g * RX_M + i] = f[i];
+    }
+}
+
+// The G segments' maps in order (one wavefront: lane l composes a run of
+// consecutive segments, then the lanes in order), applied to the start state.
+extern "C" __global__ __launch_bounds__(64) void rx_long_compose(const u32* __restrict__ seg_maps, long long G,
+                                                                 unsigned char* __restrict__ out) {
+    const int lane = threadIdx.x;
+    const long long per = (G + 63) / 64, g0 = lane * per, g1 = g0 + per < G ? g0 + per : G;
+    u32 f[RX_M];
+    bool any = false;
+    for (long long g = g0; g < g1; ++g) {
+        u32 h[RX_M];
+#pragma unroll
+        for (int i = 0; i < RX_M; ++i) h[i] = seg_maps[g * RX_M + i];
+        if (any) rx_aff_compose(f, h);
+        else {
+#pragma unroll
+            for (int i = 0; i < RX_M; ++i) f[i] = h[i];
+            any = true;
+        }
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        u32 h[RX_M];
+#pragma unroll
+        for (int i = 0; i < RX_M; ++i) h[i] = __shfl_down(any ? f[i] : 0u, d, 64);
+        const int ha = __shfl_down(any ? 1 : 0, d, 64);
+        if ((lane & (2 * d - 1)) == 0 && lane + d < 64 && ha) {
+            if (any) rx_aff_compose(f, h);
+            else {
+#pragma unroll
+                for (int i = 0; i < RX_M; ++i) f[i] = h[i];
+                any = true;
+            }
+        }
+    }
+    if (lane == 0) out[0] = rx_aff_result(f, any);
 }
 #endif
 )RX";
@@ -1470,6 +1642,7 @@ struct JitKernel {
     hipFunction_t first = nullptr;   // the skewed kernel's earliest-accept form
     bool first_words = false;
     hipFunction_t chunks = nullptr;   // chunk-parallel form (circuits of at most two words)
+    hipFunction_t long_chunks = nullptr, long_compose = nullptr;   // one long string (at most 18 words)
     int dev = -1;
     int n_state = 0, n_ops = 0;
     std::string arch;
@@ -1869,6 +2042,12 @@ int jit_compile(Program* P, const char* arch_in) {
             K->chunks = nullptr;
             (void)hipGetLastError();
         }
+        if (e == hipSuccess && K->n_state <= kLongChunkMaxState &&
+            (hipModuleGetFunction(&K->long_chunks, K->mod, "rx_long_chunks") != hipSuccess ||
+             hipModuleGetFunction(&K->long_compose, K->mod, "rx_long_compose") != hipSuccess)) {
+            K->long_chunks = K->long_compose = nullptr;
+            (void)hipGetLastError();
+        }
         if (e != hipSuccess) {
             hipModuleUnload(K->mod);
             delete K;
@@ -2031,6 +2210,46 @@ int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, 
     void* o = out;
     void* args[] = {&b, &len, &nn, &o};
     return (int)hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, threads, 1, 1, lds, (hipStream_t)stream, args, nullptr);
+}
+
+// Chunk length (a multiple of 16) and segments of the long-string form: about
+// 512 segments of 2,048 chunks, chunks of at least 16 bytes.
+void long_chunk_shape(int64_t length, int64_t* Lc, int64_t* G) {
+    int64_t c = (length + 2048 * 512 - 1) / (2048 * 512);
+    c = (c + 15) / 16 * 16;
+    if (c < 16) c = 16;
+    *Lc = c;
+    *G = (length + 2048 * c - 1) / (2048 * c);
+}
+
+int64_t long_chunk_work_bytes(const Program* P, int64_t length) {
+    const JitKernel* K = static_cast<const JitKernel*>(P->jit);
+    if (!K || !K->long_chunks) return -1;
+    int64_t Lc, G;
+    long_chunk_shape(length, &Lc, &G);
+    return 4 * G * (K->n_state + 1);
+}
+
+int launch_long_chunks(const Program* P, const uint8_t* bytes, int64_t length, void* work, uint8_t* out,
+                       void* stream) {
+    const JitKernel* K = static_cast<const JitKernel*>(P->jit);
+    if (!K || !K->long_chunks || !K->long_compose) return (int)hipErrorInvalidValue;
+    int64_t Lc, G;
+    long_chunk_shape(length, &Lc, &G);
+    if (G > 0x7fffffffll) return (int)hipErrorInvalidValue;
+    const unsigned lds = (unsigned)(4 * 2048 * (K->n_state + 1));
+    long long len = length, lc = Lc, gg = G;
+    const void* b = bytes;
+    void* w = work;
+    void* o = out;
+    if (G > 0) {
+        void* args[] = {&b, &len, &lc, &w};
+        if (hipError_t e = hipModuleLaunchKernel(K->long_chunks, (unsigned)G, 1, 1, 64, 1, 1, lds, (hipStream_t)stream,
+                                                 args, nullptr))
+            return (int)e;
+    }
+    void* args2[] = {&w, &gg, &o};
+    return (int)hipModuleLaunchKernel(K->long_compose, 1, 1, 1, 64, 1, 1, 0, (hipStream_t)stream, args2, nullptr);
 }
 
 bool jit_chunks_ready(const Program* P) {

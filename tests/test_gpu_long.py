@@ -215,3 +215,44 @@ def test_first_long_pathological(dev, family, k):
     for chunks in (1, 8, 40):
         assert first_long(p, s.data[:n].copy(), dev, chunks) == -1
         assert first_long(p, s.data[n:].copy(), dev, chunks) == n
+
+
+def test_long_circuit_chunks(dev):
+    """With a compiled circuit of at most 18 words and the default chunking, rx_match_long runs the string
+    as circuit chunks (each chunk an affine map of the state words): the ~200-node searched expression on
+    strings of 0 .. 4 MB, rejected and with a member planted at the start, across a segment boundary and at
+    the end; small programs anchored and searched on {a, b} text; the 4,096-node families by their closed
+    form.  Every bit equals the oracle's and the table form's (an explicit chunk count)."""
+    from paper_1108_3126_amd import rx
+
+    prog = W.single_program(1)
+    p = rx.compile(prog.ast, prog.root, prog.classes, True).upload(dev).jit()
+    assert p.jit_stats()["state_words"] <= 18
+    s, _ = W.single_strings(prog, seed=8, n=16384, length=256, plant_frac=0.0)
+    bits = oracle.match(prog.ast, prog.root, prog.classes, True, s.data, s.offsets, threads=8)
+    clean = np.concatenate([s.data[i * 256:(i + 1) * 256] for i in np.nonzero(bits == 0)[0]])
+    w, _ = W.single_strings(prog, seed=9, n=1, length=256, plant_frac=1.0)
+    for length in (0, 1, 300, 70_001, 2048 * 16 * 3 + 7, len(clean)):
+        base = np.resize(clean, length)
+        for at in ([None, 0, length // 2, 2048 * 16 - 100, length - 256] if length >= 2048 * 16 else [None]):
+            data = base.copy()
+            if at is not None:
+                data[at:at + 256] = w.data
+            want = oracle_bit(prog, True, data)
+            assert long_bit(p, data, dev) == want, (length, at)
+            if length <= 70_001:
+                assert long_bit(p, data, dev, 64) == want, (length, at, "table")
+    rng = np.random.default_rng(7)
+    for seed in range(40):
+        sp = W.small_program(seed)
+        for search in (False, True):
+            q = rx.compile(sp.ast, sp.root, sp.classes, search).upload(dev).jit()
+            for length in (0, 5, 600, 40_000):
+                data = np.frombuffer(b"ab", np.uint8)[rng.integers(0, 2, size=length)].astype(np.uint8)
+                assert long_bit(q, data, dev) == oracle_bit(sp, search, data), (seed, search, length)
+    for family, k in (("nested", 819), ("altstar", 585)):
+        pk = W.pathological_program(family, k)
+        q = rx.compile(pk.ast, pk.root).upload(dev).jit()
+        for n in (1, 1000, 100_000):
+            t = W.pathological_strings(family, n, count=2)
+            assert long_bit(q, t.data[:n], dev) == 0 and long_bit(q, t.data[n:], dev) == 1, (family, n)

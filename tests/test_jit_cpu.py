@@ -263,3 +263,110 @@ def test_chunk_parallel_small_patterns(pattern, search):
         s = fixed_strings(rng, n, length, b"abcxyzw")
         want = oracle.match(ast, root, classes, search, s.data, s.offsets)
         assert np.array_equal(run(s.data, length, n), want), length
+
+
+LONG_DRIVER = r"""
+// rx_match_long's circuit form on the host: every segment of 2,048 chunks,
+// every lane's NS + 1 runs (the same rx_aff_run as on the device), the maps
+// composed in chunk order, then applied to the start state.
+extern "C" int rx_cpu_long(const unsigned char* bytes, long long length, long long Lc, unsigned char* out) {
+    u32 f[RX_M];
+    bool any = false;
+    for (long long base = 0; base < length; base += 2048 * Lc) {
+        const long long seglen = length - base < 2048 * Lc ? length - base : 2048 * Lc;
+        for (int lane = 0; lane < 64; ++lane) {
+            u32 maps[32][RX_M];
+            for (int r = 0; r < RX_M; ++r) {
+                u32 x[32];
+                rx_aff_run(bytes + base, seglen, Lc, lane, r, x);
+                for (int j = 0; j < 32; ++j) maps[j][r] = x[j];
+            }
+            for (int j = 0; j < 32; ++j) {
+                if ((32ll * lane + j) * Lc >= seglen) break;
+                if (any) rx_aff_compose(f, maps[j]);
+                else {
+                    for (int i = 0; i < RX_M; ++i) f[i] = maps[j][i];
+                    any = true;
+                }
+            }
+        }
+    }
+    out[0] = rx_aff_result(f, any);
+    return 0;
+}
+"""
+
+
+def cpu_long(p: rx.Program):
+    src = p.jit_source()
+    host_part = src.split("// ---- device kernel ----")[0]
+    code = "#define __device__\n#define __forceinline__ inline\n" + PERM_CPU + host_part + LONG_DRIVER
+    d = tempfile.mkdtemp(prefix="rxlong")
+    cpp, so = os.path.join(d, "c.cpp"), os.path.join(d, "c.so")
+    open(cpp, "w").write(code)
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-w", "-o", so, cpp])
+    lib = ctypes.CDLL(so)
+    lib.rx_cpu_long.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_longlong, ctypes.c_void_p]
+
+    def run(data, lc=16):
+        data = np.ascontiguousarray(data, dtype=np.uint8)
+        out = np.zeros(1, np.uint8)
+        lib.rx_cpu_long(data.ctypes.data if data.size else None, data.size, lc, out.ctypes.data)
+        return int(out[0])
+
+    return run
+
+
+def test_long_circuit_chunks_single_program():
+    """One long string as circuit chunks, each an affine map of the state words (the step's updates are ORs
+    of terms reading at most one word, Def. 5.1): the ~200-node searched expression (17 words) on text with
+    and without a planted member, at lengths that leave partial segments and chunks, chunks of 16 and 48
+    bytes; the oracle's bit every time."""
+    prog = W.single_program(1)
+    p = rx.compile(prog.ast, prog.root, prog.classes, True)
+    words = int(p.jit_source().split("#define RX_NS ", 1)[1].split()[0])
+    assert words <= 18
+    run = cpu_long(p)
+    pieces, planted = W.single_strings(prog, seed=31, n=600, length=256, plant_frac=0.05)
+    bits = oracle.match(prog.ast, prog.root, prog.classes, True, pieces.data, pieces.offsets)
+    clean = np.concatenate([pieces.data[i * 256:(i + 1) * 256] for i in np.nonzero(bits == 0)[0][:200]])
+    member = pieces.data[planted[0] * 256:(planted[0] + 1) * 256]
+    rng = np.random.default_rng(5)
+    for length in (0, 1, 255, 4096, 40_000, 70_001):
+        text = np.resize(clean, length)
+        for plant in (False, True):
+            t = text.copy()
+            if plant and length >= 256:
+                at = int(rng.integers(0, length - 255))
+                t[at:at + 256] = member
+            want = int(oracle.match(prog.ast, prog.root, prog.classes, True, t, np.array([0, length], np.int64))[0])
+            for lc in (16, 48):
+                assert run(t, lc) == want, (length, plant, lc)
+
+
+@pytest.mark.parametrize("pattern,search", [(b"(ab)*c", False), (b"a(b|c)*d", False), (b"(x|y|z)*w", False),
+                                            (b"abc", True)])
+def test_long_circuit_chunks_small_patterns(pattern, search):
+    """Anchored and searched patterns whose result depends on the whole string (a member, a member with
+    one byte changed at a chunk boundary or inside a chunk), lengths across segment boundaries."""
+    p = rx.compile_regex(pattern, search=search)
+    ast, root, classes = rx.parse(pattern)
+    run = cpu_long(p)
+    rng = np.random.default_rng(len(pattern))
+    for length in (3, 17, 2048 * 16 + 5, 2 * 2048 * 16 + 33):
+        if pattern == b"(ab)*c":
+            base = np.frombuffer((b"ab" * length)[:length - 1] + b"c", np.uint8) if length % 2 else None
+        elif pattern == b"a(b|c)*d":
+            base = np.frombuffer(b"a" + bytes(rng.choice(list(b"bc"), size=length - 2)) + b"d", np.uint8)
+        elif pattern == b"(x|y|z)*w":
+            base = np.frombuffer(bytes(rng.choice(list(b"xyz"), size=length - 1)) + b"w", np.uint8)
+        else:
+            base = np.frombuffer(bytes(rng.choice(list(b"abcx"), size=length)), np.uint8)
+        if base is None:
+            continue
+        for flip in (None, 0, length // 2, 16 * 2048, length - 1):
+            t = base.copy()
+            if flip is not None and flip < length:
+                t[flip] = ord("q")
+            want = int(oracle.match(ast, root, classes, search, t, np.array([0, length], np.int64))[0])
+            assert run(t, 16) == want, (length, flip)
