@@ -287,7 +287,7 @@ int rx_match_first_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t
  * d_out: caller-owned device byte, 0 or 1.  Asynchronous on stream: d_bytes
  * and d_work stay in use until the stream passes the call; allocates
  * nothing.  Length 0 gives the nullable bit.
- * With chunks = 0 and a compiled circuit (rx_program_jit) of at most 18 state
+ * With chunks = 0 and a compiled circuit (rx_program_jit) of at most 31 state
  * words, the string runs as circuit chunks instead: every update of the
  * circuit's step (and its accept bit) is an OR of terms that read at most one
  * state word, so a chunk maps a state to the image of the empty state OR the
@@ -295,7 +295,9 @@ int rx_match_first_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t
  * each chunk from the empty state and from every word alone (bit j of a
  * circuit word = chunk j of a lane), composes the chunks' maps in order, and a
  * second launch composes the segments' maps and applies them to the start
- * state.  rx_match_long_workspace(.., chunks = 0, ..) covers both forms.
+ * state; the workspace holds every chunk's map (4 (words + 1) bytes per chunk,
+ * about 2,048 x 512 chunks for strings over 32 MiB) and the segments' maps.
+ * rx_match_long_workspace(.., chunks = 0, ..) covers both forms.
  * Errors: RX_EINVAL (NULL buffers, negative sizes, short workspace),
  * RX_ENOTUPLOADED, RX_ETOOBIG (sets above 128 words), RX_EHIP. */
 int rx_match_long_workspace(const rx_program* prog, int64_t length, int32_t chunks, size_t* bytes);

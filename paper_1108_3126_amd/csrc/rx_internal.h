@@ -227,7 +227,7 @@ bool jit_chunks_ready(const Program* P);
 // words: the chunk maps are affine, NS + 1 runs each): the workspace it needs
 // (-1: no such kernel for this program) and the launch (segments, then their
 // composition, on `stream`).
-constexpr int kLongChunkMaxState = 18;   // 2,048 chunk maps of NS + 1 words in LDS
+constexpr int kLongChunkMaxState = 31;   // a state as bits 0 .. NS - 1 of a word, the accept bit 31
 int64_t long_chunk_work_bytes(const Program* P, int64_t length);
 int launch_long_chunks(const Program* P, const uint8_t* bytes, int64_t length, void* work, uint8_t* out,
                        void* stream);

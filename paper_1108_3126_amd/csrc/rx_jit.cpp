@@ -569,7 +569,7 @@ __device__ __forceinline__ unsigned char rx_chunk_result(u32 f) {
 }
 #endif
 
-#if RX_NS <= 18
+#if RX_NS <= 31
 #define RX_M (RX_NS + 1)
 // Affine maps of the state words.  Every update of the step is an OR of
 // terms that read at most one word (a leaf's word AND its label, or a label
@@ -672,25 +672,28 @@ extern "C" __global__ __launch_bounds__(64) void rx_sliced_chunks(const unsigned
 }
 #endif
 
-#if RX_NS <= 18
+#if RX_NS <= 31
 // One long string: one wavefront per segment of 2,048 chunks of Lc bytes.
 // Lane l runs the NS + 1 runs of its 32 chunks, keeping every chunk's map in
-// LDS (2,048 x (NS + 1) words), composes its chunks in order, and the lanes'
-// maps compose in lane order in six shuffle steps; the segment's map goes to
+// the workspace (chunk_maps, 2,048 x (NS + 1) words per segment; word r of
+// chunk 32 l + j at ((g (NS + 1) + r) 32 + j) 64 + l, so a wavefront's stores
+// and loads are coalesced), composes its chunks in order, and the lanes' maps
+// compose in lane order in six shuffle steps; the segment's map goes to
 // seg_maps[g * (NS + 1) ..].
 extern "C" __global__ __launch_bounds__(64) void rx_long_chunks(const unsigned char* __restrict__ bytes,
                                                                 long long length, long long Lc,
-                                                                u32* __restrict__ seg_maps) {
-    extern __shared__ u32 rx_maps[];
+                                                                u32* __restrict__ seg_maps,
+                                                                u32* __restrict__ chunk_maps) {
     const long long g = blockIdx.x;
     const int lane = threadIdx.x;
     const long long base = g * 2048 * Lc;
     const long long seglen = length - base < 2048 * Lc ? length - base : 2048 * Lc;
+    u32* maps = chunk_maps + g * RX_M * 2048;
     for (int r = 0; r < RX_M; ++r) {
         u32 x[32];
         rx_aff_run(bytes + base, seglen, Lc, lane, r, x);
 #pragma unroll
-        for (int j = 0; j < 32; ++j) rx_maps[(32 * lane + j) * RX_M + r] = x[j];
+        for (int j = 0; j < 32; ++j) maps[(r * 32 + j) * 64 + lane] = x[j];
     }
     u32 f[RX_M];
     bool any = false;
@@ -698,7 +701,7 @@ extern "C" __global__ __launch_bounds__(64) void rx_long_chunks(const unsigned c
         if ((32ll * lane + j) * Lc >= seglen) break;
         u32 h[RX_M];
 #pragma unroll
-        for (int i = 0; i < RX_M; ++i) h[i] = rx_maps[(32 * lane + j) * RX_M + i];
+        for (int i = 0; i < RX_M; ++i) h[i] = maps[(i * 32 + j) * 64 + lane];
         if (any) rx_aff_compose(f, h);
         else {
 #pragma unroll
@@ -2222,12 +2225,14 @@ void long_chunk_shape(int64_t length, int64_t* Lc, int64_t* G) {
     *G = (length + 2048 * c - 1) / (2048 * c);
 }
 
+// The segments' maps, then every chunk's map (256-byte aligned).
 int64_t long_chunk_work_bytes(const Program* P, int64_t length) {
     const JitKernel* K = static_cast<const JitKernel*>(P->jit);
     if (!K || !K->long_chunks) return -1;
     int64_t Lc, G;
     long_chunk_shape(length, &Lc, &G);
-    return 4 * G * (K->n_state + 1);
+    const int64_t seg = (4 * G * (K->n_state + 1) + 255) & ~int64_t(255);
+    return seg + 4 * G * 2048 * (K->n_state + 1);
 }
 
 int launch_long_chunks(const Program* P, const uint8_t* bytes, int64_t length, void* work, uint8_t* out,
@@ -2237,14 +2242,14 @@ int launch_long_chunks(const Program* P, const uint8_t* bytes, int64_t length, v
     int64_t Lc, G;
     long_chunk_shape(length, &Lc, &G);
     if (G > 0x7fffffffll) return (int)hipErrorInvalidValue;
-    const unsigned lds = (unsigned)(4 * 2048 * (K->n_state + 1));
     long long len = length, lc = Lc, gg = G;
     const void* b = bytes;
     void* w = work;
+    void* cm = static_cast<uint8_t*>(work) + ((4 * G * (K->n_state + 1) + 255) & ~int64_t(255));
     void* o = out;
     if (G > 0) {
-        void* args[] = {&b, &len, &lc, &w};
-        if (hipError_t e = hipModuleLaunchKernel(K->long_chunks, (unsigned)G, 1, 1, 64, 1, 1, lds, (hipStream_t)stream,
+        void* args[] = {&b, &len, &lc, &w, &cm};
+        if (hipError_t e = hipModuleLaunchKernel(K->long_chunks, (unsigned)G, 1, 1, 64, 1, 1, 0, (hipStream_t)stream,
                                                  args, nullptr))
             return (int)e;
     }

@@ -325,7 +325,7 @@ def test_long_circuit_chunks_single_program():
     prog = W.single_program(1)
     p = rx.compile(prog.ast, prog.root, prog.classes, True)
     words = int(p.jit_source().split("#define RX_NS ", 1)[1].split()[0])
-    assert words <= 18
+    assert words <= 31
     run = cpu_long(p)
     pieces, planted = W.single_strings(prog, seed=31, n=600, length=256, plant_frac=0.05)
     bits = oracle.match(prog.ast, prog.root, prog.classes, True, pieces.data, pieces.offsets)
