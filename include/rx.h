@@ -296,7 +296,8 @@ int rx_match_first_fixed(const rx_program* prog, const uint8_t* d_bytes, int64_t
  * circuit word = chunk j of a lane), composes the chunks' maps in order, and a
  * second launch composes the segments' maps and applies them to the start
  * state; the workspace holds every chunk's map (4 (words + 1) bytes per chunk,
- * about 2,048 x 512 chunks for strings over 32 MiB) and the segments' maps.
+ * chunks of at least 16 bytes, at most about 2,048 x 2,048 of them) and the
+ * segments' maps.
  * rx_match_long_workspace(.., chunks = 0, ..) covers both forms.
  * Errors: RX_EINVAL (NULL buffers, negative sizes, short workspace),
  * RX_ENOTUPLOADED, RX_ETOOBIG (sets above 128 words), RX_EHIP. */

@@ -2215,10 +2215,11 @@ int launch_sliced_fixed(const Program* P, const uint8_t* bytes, int64_t length, 
     return (int)hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, threads, 1, 1, lds, (hipStream_t)stream, args, nullptr);
 }
 
-// Chunk length (a multiple of 16) and segments of the long-string form: about
-// 512 segments of 2,048 chunks, chunks of at least 16 bytes.
+// Chunk length (a multiple of 16) and segments of the long-string form: up to
+// about 2,048 segments of 2,048 chunks (two wavefronts per SIMD), chunks of
+// at least 16 bytes.
 void long_chunk_shape(int64_t length, int64_t* Lc, int64_t* G) {
-    int64_t c = (length + 2048 * 512 - 1) / (2048 * 512);
+    int64_t c = (length + 2048 * 2048 - 1) / (2048 * 2048);
     c = (c + 15) / 16 * 16;
     if (c < 16) c = 16;
     *Lc = c;
