@@ -243,7 +243,7 @@ def test_long_circuit_chunks(dev):
             if length <= 70_001:
                 assert long_bit(p, data, dev, 64) == want, (length, at, "table")
     rng = np.random.default_rng(7)
-    for seed in range(40):
+    for seed in range(12):
         sp = W.small_program(seed)
         for search in (False, True):
             q = rx.compile(sp.ast, sp.root, sp.classes, search).upload(dev).jit()
