@@ -317,9 +317,12 @@ def test_chunk_parallel_pathological(dev):
         p = rx.compile(prog.ast, prog.root).upload(dev).jit()
         assert p.jit_stats()["state_words"] <= 2
         for length in (1, 33, 1008, 4097, 100_000):
-            s = W.pathological_strings(family, length, count=64)
-            want = oracle_match(prog, s)
-            assert want[:32].sum() == 0 and want[32:].all()
+            s = W.pathological_strings(family, length, count=64 if length < 10_000 else 8)
+            # the closed form a^(n-1) t everywhere; the oracle as well up to 4,097 bytes
+            half = s.n // 2
+            want = np.concatenate([np.zeros(half, np.uint8), np.ones(s.n - half, np.uint8)])
+            if length < 10_000:
+                assert np.array_equal(oracle_match(prog, s), want)
             got = fixed_match(p, s, length, dev, rx.VARIANT_CHUNKS)
             assert np.array_equal(got, want), (family, length)
             # one byte into the buffer: every string unaligned
