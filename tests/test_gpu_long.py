@@ -242,6 +242,10 @@ def test_long_circuit_chunks(dev):
             assert long_bit(p, data, dev) == want, (length, at)
             if length <= 70_001:
                 assert long_bit(p, data, dev, 64) == want, (length, at, "table")
+            if length == 2048 * 16 * 3 + 7:
+                # three bytes into the buffer: every chunk unaligned
+                buf = torch.from_numpy(np.concatenate([np.zeros(3, np.uint8), data])).to(dev)
+                assert int(rx.match_long(p, buf[3:], length).cpu().numpy()[0]) == want, (length, at, "unaligned")
     rng = np.random.default_rng(7)
     for seed in range(6):
         sp = W.small_program(seed)
