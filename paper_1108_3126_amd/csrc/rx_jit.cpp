@@ -588,52 +588,115 @@ __device__ __forceinline__ void rx_aff_compose(u32 (&f)[RX_M], const u32 (&g)[RX
     for (int i = 0; i < RX_M; ++i) f[i] = rx_aff_apply(g, f[i] & 0x7fffffffu);
 }
 
-// Run r (0: from the empty state, k + 1: from word k alone) of chunks
-// 32 lane .. 32 lane + 31 (Lc bytes each, bit j = chunk 32 lane + j) of the
-// seglen bytes at s; x[j] gets chunk j's image under the run (bit k: word k,
-// bit 31: the accept bit after its last byte).
-__device__ __forceinline__ void rx_aff_run(const unsigned char* s, long long seglen, long long Lc, int lane, int r,
-                                           u32 (&x)[32]) {
-    int len[32];   // Lc < 2^31 (the host allows strings of up to 2^40 bytes)
+// The lengths (at most Lc) of chunks 32 lane .. 32 lane + 31 of a segment of
+// seglen bytes.
+__device__ __forceinline__ void rx_aff_lens(long long seglen, long long Lc, int lane, int (&len)[32]) {
 #pragma unroll
     for (int j = 0; j < 32; ++j) {
         const long long start = (32ll * lane + j) * Lc;
-        len[j] = start < seglen ? (int)(seglen - start < Lc ? seglen - start : Lc) : 0;
+        len[j] = start < seglen ? (int)(seglen - start < Lc ? seglen - start : Lc) : 0;   // Lc < 2^31
     }
-    u32 st[RX_NS], acc = 0u;
+}
+
+// Positions p .. p + 15 of those chunks as bit planes: y[q][8 i + b] is bit b
+// of byte 4 q + i of every chunk (bit j = chunk 32 lane + j).
+__device__ __forceinline__ void rx_aff_planes(const unsigned char* s, long long Lc, int lane, const int (&len)[32],
+                                              long long p, u32 (&y)[4][32]) {
 #pragma unroll
-    for (int k = 0; k < RX_NS; ++k) st[k] = r == k + 1 ? 0xffffffffu : 0u;
-    for (long long p = 0; p < Lc && p < len[0]; p += 16) {
-        u32 win[32][4];
+    for (int j = 0; j < 32; ++j) {
+        u32 w[4];
+        rx_chunk_window16(s + (32ll * lane + j) * Lc, len[j], p, w);
 #pragma unroll
-        for (int j = 0; j < 32; ++j) rx_chunk_window16(s + (32ll * lane + j) * Lc, len[j], p, win[j]);
+        for (int q = 0; q < 4; ++q) y[q][j] = w[q];
+    }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            u32 y[32];
+    for (int q = 0; q < 4; ++q) rx_transpose32(y[q]);
+}
+
+// The chunks that still have bytes at positions p .. p + 15 (vm[t]: bit j
+// for chunk 32 lane + j at position p + t).
+__device__ __forceinline__ void rx_aff_masks(const int (&len)[32], long long p, u32 (&vm)[16]) {
 #pragma unroll
-            for (int j = 0; j < 32; ++j) y[j] = win[j][q];
-            rx_transpose32(y);
+    for (int t = 0; t < 16; ++t) {
+        u32 v = 0u;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const long long pos = p + 4 * q + i;
-                u32 v = 0u;
+        for (int j = 0; j < 32; ++j) v |= (len[j] > p + t ? 1u : 0u) << j;
+        vm[t] = v;
+    }
+}
+
+// The circuit over those 16 positions, each chunk's state frozen once it has
+// ended.
+__device__ __forceinline__ void rx_aff_steps(const u32 (&y)[4][32], const u32 (&vm)[16], u32 (&st)[RX_NS],
+                                             u32& acc) {
 #pragma unroll
-                for (int j = 0; j < 32; ++j) v |= (len[j] > pos ? 1u : 0u) << j;
-                u32 ns[RX_NS];
+    for (int q = 0; q < 4; ++q) {
 #pragma unroll
-                for (int k = 0; k < RX_NS; ++k) ns[k] = st[k];
-                u32 a = acc;
-                rx_step(ns, a, y[8 * i], y[8 * i + 1], y[8 * i + 2], y[8 * i + 3], y[8 * i + 4], y[8 * i + 5],
-                        y[8 * i + 6], y[8 * i + 7]);
+        for (int i = 0; i < 4; ++i) {
+            const u32 v = vm[4 * q + i];
+            u32 ns[RX_NS];
 #pragma unroll
-                for (int k = 0; k < RX_NS; ++k) st[k] = (ns[k] & v) | (st[k] & ~v);
-                acc = (a & v) | (acc & ~v);
-            }
+            for (int k = 0; k < RX_NS; ++k) ns[k] = st[k];
+            u32 a = acc;
+            rx_step(ns, a, y[q][8 * i], y[q][8 * i + 1], y[q][8 * i + 2], y[q][8 * i + 3], y[q][8 * i + 4],
+                    y[q][8 * i + 5], y[q][8 * i + 6], y[q][8 * i + 7]);
+#pragma unroll
+            for (int k = 0; k < RX_NS; ++k) st[k] = (ns[k] & v) | (st[k] & ~v);
+            acc = (a & v) | (acc & ~v);
         }
     }
+}
+
+// Word r of the maps of the lane's 32 chunks from a run's final words: bit k
+// word k, bit 31 the accept bit, to out[(r * 32 + j) * stride].
+__device__ __forceinline__ void rx_aff_store(const u32 (&st)[RX_NS], u32 acc, int r, u32* out, int stride) {
+    u32 x[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k) x[k] = k < RX_NS ? st[k] : k == 31 ? acc : 0u;
     rx_transpose32(x);
+#pragma unroll
+    for (int j = 0; j < 32; ++j) out[(r * 32 + j) * stride] = x[j];
+}
+
+// The maps of chunks 32 lane .. 32 lane + 31 of the seglen bytes at s: run r
+// (0: from the empty state, k + 1: from word k alone) gives word r of every
+// chunk's map, written to out[(r * 32 + j) * stride] for chunk 32 lane + j
+// (bit k: word k after the chunk, bit 31: the accept bit after its last
+// byte).  Chunks of 16 bytes are one window: its planes are made once and
+// every run reuses them (a loop of its own, so the other form's values are
+// not live there).
+__device__ __forceinline__ void rx_aff_lane_maps(const unsigned char* s, long long seglen, long long Lc, int lane,
+                                                 u32* out, int stride) {
+    int len[32];
+    rx_aff_lens(seglen, Lc, lane, len);
+    u32 y[4][32], vm[16];
+    if (Lc == 16) {
+        // one window: its planes and masks made once, kept for every run
+        const bool live = len[0] > 0;
+        rx_aff_planes(s, Lc, lane, len, 0, y);
+        rx_aff_masks(len, 0, vm);
+#pragma clang loop unroll(disable)
+        for (int r = 0; r < RX_M; ++r) {
+            u32 st[RX_NS], acc = 0u;
+#pragma unroll
+            for (int k = 0; k < RX_NS; ++k) st[k] = r == k + 1 ? 0xffffffffu : 0u;
+            if (live) rx_aff_steps(y, vm, st, acc);
+            rx_aff_store(st, acc, r, out, stride);
+        }
+        return;
+    }
+#pragma clang loop unroll(disable)
+    for (int r = 0; r < RX_M; ++r) {
+        u32 st[RX_NS], acc = 0u;
+#pragma unroll
+        for (int k = 0; k < RX_NS; ++k) st[k] = r == k + 1 ? 0xffffffffu : 0u;
+        for (long long p = 0; p < Lc && p < len[0]; p += 16) {
+            rx_aff_planes(s, Lc, lane, len, p, y);
+            rx_aff_masks(len, p, vm);
+            rx_aff_steps(y, vm, st, acc);
+        }
+        rx_aff_store(st, acc, r, out, stride);
+    }
 }
 
 // The start state as a word set, and the result of a string from the
@@ -689,12 +752,7 @@ extern "C" __global__ __launch_bounds__(64) void rx_long_chunks(const unsigned c
     const long long base = g * 2048 * Lc;
     const long long seglen = length - base < 2048 * Lc ? length - base : 2048 * Lc;
     u32* maps = chunk_maps + g * RX_M * 2048;
-    for (int r = 0; r < RX_M; ++r) {
-        u32 x[32];
-        rx_aff_run(bytes + base, seglen, Lc, lane, r, x);
-#pragma unroll
-        for (int j = 0; j < 32; ++j) maps[(r * 32 + j) * 64 + lane] = x[j];
-    }
+    rx_aff_lane_maps(bytes + base, seglen, Lc, lane, maps + lane, 64);
     u32 f[RX_M];
     bool any = false;
     for (int j = 0; j < 32; ++j) {

@@ -267,7 +267,7 @@ def test_chunk_parallel_small_patterns(pattern, search):
 
 LONG_DRIVER = r"""
 // rx_match_long's circuit form on the host: every segment of 2,048 chunks,
-// every lane's NS + 1 runs (the same rx_aff_run as on the device), the maps
+// every lane's NS + 1 runs (the same rx_aff_lane_maps as on the device), the maps
 // composed in chunk order, then applied to the start state.
 extern "C" int rx_cpu_long(const unsigned char* bytes, long long length, long long Lc, unsigned char* out) {
     u32 f[RX_M];
@@ -275,12 +275,10 @@ extern "C" int rx_cpu_long(const unsigned char* bytes, long long length, long lo
     for (long long base = 0; base < length; base += 2048 * Lc) {
         const long long seglen = length - base < 2048 * Lc ? length - base : 2048 * Lc;
         for (int lane = 0; lane < 64; ++lane) {
-            u32 maps[32][RX_M];
-            for (int r = 0; r < RX_M; ++r) {
-                u32 x[32];
-                rx_aff_run(bytes + base, seglen, Lc, lane, r, x);
-                for (int j = 0; j < 32; ++j) maps[j][r] = x[j];
-            }
+            u32 flat[RX_M * 32], maps[32][RX_M];
+            rx_aff_lane_maps(bytes + base, seglen, Lc, lane, flat, 1);
+            for (int r = 0; r < RX_M; ++r)
+                for (int j = 0; j < 32; ++j) maps[j][r] = flat[r * 32 + j];
             for (int j = 0; j < 32; ++j) {
                 if ((32ll * lane + j) * Lc >= seglen) break;
                 if (any) rx_aff_compose(f, maps[j]);
