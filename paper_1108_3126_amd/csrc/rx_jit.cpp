@@ -1703,7 +1703,7 @@ struct JitKernel {
     hipFunction_t first = nullptr;   // the skewed kernel's earliest-accept form
     bool first_words = false;
     hipFunction_t chunks = nullptr;   // chunk-parallel form (circuits of at most two words)
-    hipFunction_t long_chunks = nullptr, long_compose = nullptr;   // one long string (at most 18 words)
+    hipFunction_t long_chunks = nullptr, long_compose = nullptr;   // one long string (at most 31 words)
     int dev = -1;
     int n_state = 0, n_ops = 0;
     std::string arch;
